@@ -1,0 +1,192 @@
+"""Throughput benchmark of the sliced QAOA amplitude contraction on one GPU.
+
+Workload (default): random 3-regular graph, n = 120 qubits, QAOA depth 1,
+8 output bitstrings batched, cut size k = the smallest k whose searched cut
+keeps every slice tensor at rank <= 26; seeded synthetic instance.  One step
+is one qtn_contract over all 2^k slices of all 8 bitstrings (the whole hot
+path: slice set-up, every contraction step, the FP64 slice sum).  The mixed
+form (FP32 storage and arithmetic with per-slice power-of-two rescaling) is
+the headline; the plain FP64 GPU contraction is timed beside it.
+
+Prints one JSON line.  Single GPU only.
+"""
+import argparse
+import json
+import math
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "slices/sec + amplitudes/sec, n=120 p=1 3-reg QAOA, mixed-prec vs FP64 GPU"
+HBM_PEAK_GBS = 8000.0
+
+
+def _oracle_worker(args):
+    """One amplitude on one host core (the paper's one-subgraph-per-core scheme)."""
+    n, edges, p, gamma, beta, x, cut, order, slices = args
+    from oracle import qaoa as Q
+    t = time.perf_counter()
+    if cut:
+        val = sum(Q.slice_partial(n, edges, p, gamma, beta, x, cut, s, order=order) for s in slices)
+    else:
+        val = Q.ve_amplitude(n, edges, p, gamma, beta, x, order=order)
+    return val, time.perf_counter() - t
+
+
+def cpu_baseline(inst, cut, order, budget_s=20.0):
+    """Times the oracle on a bounded sample of the same workload."""
+    cores = max(1, min(16, os.cpu_count() or 1))
+    k = len(cut)
+    # one probe to size the sample
+    slices_per_job = 1 if k else 0
+    probe = _oracle_worker((inst.n, inst.edges, inst.p, inst.gamma, inst.beta, inst.bitstrings[0],
+                            cut, order, range(slices_per_job) if k else None))
+    per_job = max(probe[1], 1e-3)
+    jobs = max(cores, int(budget_s / per_job))
+    jobs = min(jobs, 4 * cores * 8)
+    B = inst.bitstrings.shape[0]
+    work = []
+    for j in range(jobs):
+        b = j % B
+        sl = [j // B % (1 << k)] if k else None
+        work.append((inst.n, inst.edges, inst.p, inst.gamma, inst.beta, inst.bitstrings[b],
+                     cut, order, sl))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, work)
+    wall = time.perf_counter() - t0
+    vals = [r[0] for r in res]
+    if k:
+        value = jobs / wall                     # slice-contractions per second
+        unit = "slices/s"
+        amps = value / (1 << k)
+    else:
+        value = jobs / wall
+        unit = "amplitudes/s"
+        amps = value
+    return {"value": value, "unit": unit, "amplitudes_per_sec": amps, "cores": cores,
+            "kind": "oracle", "sample": "%d %s of the workload (bitstrings cycled), complex128 "
+            "variable elimination with the plan's order and cut, %d worker processes" %
+            (jobs, "slices" if k else "uncut amplitudes", cores),
+            "cpu_seconds": sum(r[1] for r in res), "wall_seconds": wall}, vals
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="qaoa_n120_p1_b8")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--slices-per-wave", type=int, default=4096)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the sliced contraction shards by slice range "
+              "across GPUs, which this build does not launch (requested --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from instances import workload_instance
+    from paper_2010_14962_amd import plan_instance, qtn_plan
+
+    torch.cuda.set_device(0)
+    inst = workload_instance(args.workload, seed=args.seed)
+    w = inst.meta
+    t0 = time.perf_counter()
+    mixed = plan_instance(inst, k=w["k"] if w["k"] is not None else -1,
+                          max_rank=w["max_rank"] or 0, precision="fp32")
+    plan_s = time.perf_counter() - t0
+    cut = mixed.cut()
+    info = mixed.info()
+    k = info["k"]
+    nsl = 1 << k
+    B = inst.n_bitstrings
+    f64 = plan_instance(inst, cut_vars=cut, precision="fp64")
+    S = min(nsl, args.slices_per_wave)
+    mixed.bind_torch(S)
+    f64.bind_torch(S)
+    stream = torch.cuda.current_stream().cuda_stream
+    print("# workload %s k=%d width=%d steps=%d B=%d S=%d plan %.3fs" %
+          (args.workload, k, info["width"], info["n_steps"], B, S, plan_s), file=sys.stderr, flush=True)
+
+    def run(plan, steps, warmup, timing):
+        for _ in range(warmup):
+            plan.contract(0, nsl, stream)
+        if timing:
+            plan.set_timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = None
+        for _ in range(steps):
+            out = plan.contract(0, nsl, stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        tm = plan.timing() if timing else None
+        if timing:
+            plan.set_timing(False)
+        return el, [p.value() for p in out], tm
+
+    el, amps, tm = run(mixed, args.steps, args.warmup, True)
+    print("# mixed: %.3f ms/step" % (1e3 * el / args.steps), file=sys.stderr, flush=True)
+    n64 = args.fp64_steps or max(3, args.steps // 2)
+    el64, amps64, _ = run(f64, n64, 2, False)
+    print("# fp64: %.3f ms/step" % (1e3 * el64 / n64), file=sys.stderr, flush=True)
+
+    ms = 1e3 * el / args.steps
+    amps_per_s = B * args.steps / el
+    slices_per_s = B * nsl * args.steps / el
+    err_vs_fp64 = max(abs(a - b) / max(abs(b), 1e-300) for a, b in zip(amps, amps64))
+
+    roof = None
+    if tm and tm["launches"]:
+        avg_ms = tm["total_ms"] / tm["launches"]
+        bytes_per_launch = tm["alg_bytes"] / tm["launches"]
+        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        roof = {"kernel": "step_stream<float,true>", "bound": "hbm", "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": None, "launches": tm["launches"], "avg_launch_us": 1e3 * avg_ms,
+                "alg_bytes_per_launch": bytes_per_launch,
+                "time_share": tm["total_ms"] / (1e3 * el)}
+
+    line = {
+        "metric": METRIC, "value": amps_per_s, "unit": "amplitudes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": inst.n, "p": inst.p, "bitstrings": B,
+                   "k": k, "slices_per_amplitude": nsl, "max_slice_rank": info["width"],
+                   "seed": args.seed, "slices_per_wave": S, "graph": "random 3-regular",
+                   "precision": "fp32 + per-slice power-of-two rescale, fp64 slice sum"},
+        "slices_per_sec": slices_per_s,
+        "fp64": {"amplitudes_per_sec": B * n64 / el64, "slices_per_sec": B * nsl * n64 / el64,
+                 "ms_per_step": 1e3 * el64 / n64},
+        "mixed_over_fp64": (amps_per_s / (B * n64 / el64)),
+        "max_rel_err_mixed_vs_fp64": err_vs_fp64,
+        "plan": {"search_s": info["search_seconds"], "plan_s": plan_s,
+                 "log2_flops_per_slice": info["log2_flops"],
+                 "alg_bytes_per_slice": info["bytes_per_slice"]},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        order = mixed.order()
+        cb, vals = cpu_baseline(inst, cut, order)
+        line["cpu_baseline"] = cb
+        if k == 0:
+            errs = []
+            for j, v in enumerate(vals[:B]):
+                errs.append(abs(amps[j % B] - v) / abs(v))
+            line["max_rel_err_mixed_vs_oracle"] = max(errs)
+            line["max_rel_err_fp64_vs_oracle"] = max(abs(amps64[j % B] - v) / abs(v)
+                                                     for j, v in enumerate(vals[:B]))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

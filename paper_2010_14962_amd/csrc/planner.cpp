@@ -1,0 +1,624 @@
+// Host planner: network (Sec. II A), line graph and min-fill order (Sec. II B),
+// cut search (Sec. III B, Algorithm 1) and the slice-invariant contraction
+// schedule (Sec. III A: every slice has the same structure, Eq. (2)).
+#include "planner.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <numeric>
+#include <stdexcept>
+
+namespace qtn {
+
+// ---------------------------------------------------------------------------
+// Network: gates of the QAOA circuit as factors over binary index variables.
+// ---------------------------------------------------------------------------
+void build_network(Network &net) {
+  const uint32_t n = net.n, p = net.p;
+  net.nv = n * p;
+  net.factors.clear();
+  net.values.clear();
+  double pref = std::pow(2.0, -0.5 * (double)n);  // H^n |0^n> = 2^{-n/2} sum |v>
+  auto var = [n](uint32_t q, uint32_t l) { return (int)(l * n + q); };
+  for (uint32_t l = 0; l < p; ++l) {
+    for (auto &e : net.edges) {
+      Factor f{2, {var(e.first, l), var(e.second, l)}, 0, (int)l, -1};
+      std::vector<cd> v(4);
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          double zz = (a == b) ? 1.0 : -1.0;  // eigenvalue of Z_i Z_j
+          v[a * 2 + b] = cd(std::cos(net.gamma[l] * zz), -std::sin(net.gamma[l] * zz));
+        }
+      net.factors.push_back(f);
+      net.values.push_back(v);
+    }
+  }
+  auto rx = [](double beta, int a, int b) {
+    return a == b ? cd(std::cos(beta), 0.0) : cd(0.0, -std::sin(beta));
+  };
+  for (uint32_t l = 0; l + 1 < p; ++l) {
+    double m = std::max(std::fabs(std::cos(net.beta[l])), std::fabs(std::sin(net.beta[l])));
+    for (uint32_t q = 0; q < n; ++q) {
+      Factor f{2, {var(q, l + 1), var(q, l)}, 1, (int)l, (int)q};
+      std::vector<cd> v(4);
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) v[a * 2 + b] = rx(net.beta[l], a, b) / m;
+      pref *= m;
+      net.factors.push_back(f);
+      net.values.push_back(v);
+    }
+  }
+  {
+    const uint32_t l = p - 1;
+    double m = std::max(std::fabs(std::cos(net.beta[l])), std::fabs(std::sin(net.beta[l])));
+    for (uint32_t q = 0; q < n; ++q) {
+      Factor f{1, {var(q, l), -1}, 2, (int)l, (int)q};
+      std::vector<cd> v(2 * net.B);
+      for (uint32_t b = 0; b < net.B; ++b) {
+        int x = net.bits[(size_t)b * n + q];
+        for (int a = 0; a < 2; ++a) v[b * 2 + a] = rx(net.beta[l], x, a) / m;
+      }
+      pref *= m;
+      net.factors.push_back(f);
+      net.values.push_back(v);
+    }
+  }
+  net.prefactor = pref;
+}
+
+std::vector<std::vector<int>> line_graph(const Network &net) {
+  std::vector<std::vector<int>> adj(net.nv);
+  for (auto &f : net.factors) {
+    if (f.nv != 2) continue;
+    adj[f.v[0]].push_back(f.v[1]);
+    adj[f.v[1]].push_back(f.v[0]);
+  }
+  for (auto &a : adj) {
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+  }
+  return adj;
+}
+
+// ---------------------------------------------------------------------------
+// Min-fill elimination order on bitset adjacency.
+// ---------------------------------------------------------------------------
+EliminationResult min_fill(const std::vector<std::vector<int>> &adj,
+                           const std::vector<int> &removed) {
+  const int V = (int)adj.size();
+  const int W = (V + 63) / 64;
+  std::vector<uint64_t> nb((size_t)V * W, 0);
+  std::vector<char> alive(V, 1);
+  for (int r : removed) alive[r] = 0;
+  int remaining = 0;
+  for (int u = 0; u < V; ++u) {
+    if (!alive[u]) continue;
+    ++remaining;
+    for (int w : adj[u])
+      if (alive[w]) nb[(size_t)u * W + (w >> 6)] |= 1ull << (w & 63);
+  }
+  auto row = [&](int u) { return &nb[(size_t)u * W]; };
+  EliminationResult res;
+  std::vector<int> members;
+  while (remaining > 0) {
+    int best = -1;
+    long long bf = 0, bd = 0;
+    for (int u = 0; u < V; ++u) {
+      if (!alive[u]) continue;
+      const uint64_t *ru = row(u);
+      long long deg = 0;
+      for (int w = 0; w < W; ++w) deg += __builtin_popcountll(ru[w]);
+      long long pairs = 0;
+      for (int w = 0; w < W; ++w) {
+        uint64_t bits = ru[w];
+        while (bits) {
+          int a = (w << 6) + __builtin_ctzll(bits);
+          bits &= bits - 1;
+          const uint64_t *ra = row(a);
+          for (int x = 0; x < W; ++x) pairs += __builtin_popcountll(ra[x] & ru[x]);
+        }
+      }
+      long long fill = deg * (deg - 1) / 2 - pairs / 2;
+      if (best < 0 || fill < bf || (fill == bf && deg < bd)) {
+        best = u;
+        bf = fill;
+        bd = deg;
+      }
+    }
+    members.clear();
+    uint64_t *rb = row(best);
+    for (int w = 0; w < W; ++w) {
+      uint64_t bits = rb[w];
+      while (bits) {
+        members.push_back((w << 6) + __builtin_ctzll(bits));
+        bits &= bits - 1;
+      }
+    }
+    for (int a : members) {
+      uint64_t *ra = row(a);
+      for (int w = 0; w < W; ++w) ra[w] |= rb[w];
+      ra[a >> 6] &= ~(1ull << (a & 63));
+      ra[best >> 6] &= ~(1ull << (best & 63));
+    }
+    for (int w = 0; w < W; ++w) rb[w] = 0;
+    alive[best] = 0;
+    --remaining;
+    res.order.push_back(best);
+    res.nplus.push_back(members);
+    res.width = std::max(res.width, (int)members.size());
+    res.work += 1ull << (members.size() + 1);
+  }
+  return res;
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 and Algorithm 1.
+// ---------------------------------------------------------------------------
+uint64_t SplitMix64::next() {
+  uint64_t z = seed + (counter + 1) * 0x9E3779B97F4A7C15ull;
+  ++counter;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+namespace {
+struct Fit {
+  int width;
+  uint64_t work;
+  std::vector<int> sorted;
+  bool operator<(const Fit &o) const {
+    if (width != o.width) return width < o.width;
+    if (work != o.work) return work < o.work;
+    return sorted < o.sorted;
+  }
+};
+}  // namespace
+
+CutResult ga_cut_search(const std::vector<std::vector<int>> &adj, int M, int N,
+                        int T, uint64_t seed) {
+  const int V = (int)adj.size();
+  std::map<std::vector<int>, Fit> cache;
+  auto fitness = [&](const std::vector<int> &ind) -> const Fit & {
+    std::vector<int> s(ind);
+    std::sort(s.begin(), s.end());
+    auto it = cache.find(s);
+    if (it != cache.end()) return it->second;
+    EliminationResult r = min_fill(adj, s);
+    Fit f{r.width, r.work, s};
+    return cache.emplace(s, f).first->second;
+  };
+  CutResult out;
+  if (M <= 0 || M >= V) {
+    std::vector<int> all;
+    if (M >= V)
+      for (int v = 0; v < V; ++v) all.push_back(v);
+    const Fit &f = fitness(all);
+    out.cut = f.sorted;
+    out.width = f.width;
+    out.work = f.work;
+    return out;
+  }
+  SplitMix64 rng(seed);
+  auto contains = [](const std::vector<int> &ind, int u) {
+    return std::find(ind.begin(), ind.end(), u) != ind.end();
+  };
+  auto nonmember = [&](const std::vector<int> &ind) {
+    for (;;) {
+      int u = (int)rng.below((uint64_t)V);
+      if (!contains(ind, u)) return u;
+    }
+  };
+  std::vector<std::vector<int>> pop;
+  for (int i = 0; i < N; ++i) {
+    std::vector<int> ind;
+    while ((int)ind.size() < M) {
+      int u = (int)rng.below((uint64_t)V);
+      if (!contains(ind, u)) ind.push_back(u);
+    }
+    pop.push_back(ind);
+  }
+  auto by_fitness = [&](const std::vector<int> &a, const std::vector<int> &b) {
+    return fitness(a) < fitness(b);
+  };
+  const int h = M / 2;
+  int t = 0;
+  for (;;) {
+    std::stable_sort(pop.begin(), pop.end(), by_fitness);          // Step 1
+    for (int i = 1; i + 1 < N; i += 2) {                          // Step 2
+      auto &a = pop[i], &b = pop[i + 1];
+      for (int q = M - h; q < M; ++q) std::swap(a[q], b[q]);
+      for (auto *ind : {&a, &b})
+        for (int q = 0; q < M; ++q)
+          if (std::find(ind->begin(), ind->begin() + q, (*ind)[q]) != ind->begin() + q)
+            (*ind)[q] = nonmember(*ind);
+    }
+    if (N > 1) {                                                  // Step 3
+      int j = 1 + (int)rng.below((uint64_t)(N - 1));
+      int q = (int)rng.below((uint64_t)M);
+      pop[j][q] = nonmember(pop[j]);
+    }
+    ++t;                                                          // Step 4
+    if (t > T) break;
+  }
+  std::stable_sort(pop.begin(), pop.end(), by_fitness);            // Step 5
+  const Fit &f = fitness(pop[0]);
+  out.cut = f.sorted;
+  out.width = f.width;
+  out.work = f.work;
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Schedule: bucket elimination with fused multi-input steps.
+// ---------------------------------------------------------------------------
+uint32_t pext32(uint32_t x, uint32_t mask) {
+  uint32_t r = 0;
+  int k = 0;
+  for (int b = 0; b < 32; ++b)
+    if ((mask >> b) & 1u) r |= ((x >> b) & 1u) << k++;
+  return r;
+}
+
+InputTables input_tables(uint32_t mask, int rC, int nk) {
+  InputTables t;
+  uint32_t cm = rC >= 32 ? mask : (mask & ((1u << rC) - 1u));
+  uint32_t km = rC >= 32 ? 0 : (mask >> rC);
+  for (uint32_t c = 0; c < 256; ++c) t.lo[c] = pext32(c, cm & 255u);
+  for (uint32_t u = 0; u < 16; ++u) t.mid[u] = pext32(u << 8, cm);
+  t.hi_mask = cm >> 12;
+  t.hi_shift = (uint32_t)__builtin_popcount(cm & 4095u);
+  uint32_t sh = (uint32_t)__builtin_popcount(cm);
+  t.kap.resize((size_t)1 << nk);
+  for (uint32_t k = 0; k < (1u << nk); ++k) t.kap[k] = pext32(k, km) << sh;
+  return t;
+}
+
+Schedule build_schedule(const Network &net, const std::vector<int> &cut,
+                        const std::vector<int> &order, const PlanOpts &o) {
+  const int V = (int)net.nv;
+  Schedule s;
+  std::vector<int> pos(V, -1), cutbit(V, -1);
+  for (size_t i = 0; i < order.size(); ++i) pos[order[i]] = (int)i;
+  for (size_t b = 0; b < cut.size(); ++b) cutbit[cut[b]] = (int)b;
+  for (int v = 0; v < V; ++v)
+    if ((pos[v] < 0) == (cutbit[v] < 0))
+      throw std::runtime_error("order and cut must partition the variables");
+  auto by_pos = [&](int a, int b) { return pos[a] < pos[b]; };
+
+  // Group every factor with the earliest-eliminated of its free variables.
+  std::vector<std::vector<int>> group(V);
+  std::vector<int> scalar_group;
+  for (size_t f = 0; f < net.factors.size(); ++f) {
+    const Factor &F = net.factors[f];
+    int first = -1;
+    for (int j = 0; j < F.nv; ++j)
+      if (pos[F.v[j]] >= 0 && (first < 0 || pos[F.v[j]] < pos[first])) first = F.v[j];
+    if (first < 0)
+      scalar_group.push_back((int)f);
+    else
+      group[first].push_back((int)f);
+  }
+  auto add_tensor = [&](Tensor t) {
+    s.tensors.push_back(std::move(t));
+    return (int)s.tensors.size() - 1;
+  };
+  // Merge a group of factors into one leaf: values for every bitstring and
+  // every assignment of the cut variables it holds (Fig. 3: the cut edge
+  // carries its fixed value into the factors on both sides).
+  auto make_leaf = [&](const std::vector<int> &fs) {
+    Tensor t;
+    t.leaf = true;
+    std::vector<int> fv;
+    uint32_t sel = 0;
+    for (int f : fs) {
+      const Factor &F = net.factors[f];
+      for (int j = 0; j < F.nv; ++j) {
+        int v = F.v[j];
+        if (pos[v] >= 0) {
+          if (std::find(fv.begin(), fv.end(), v) == fv.end()) fv.push_back(v);
+        } else {
+          sel |= 1u << cutbit[v];
+        }
+      }
+      if (F.kind == 2) t.bdep = true;
+    }
+    std::sort(fv.begin(), fv.end(), by_pos);
+    if ((int)fv.size() > kLeafMaxRank) throw std::runtime_error("leaf group too large");
+    t.vars = fv;
+    t.selmask = sel;
+    t.sdep = sel != 0;
+    const int r = (int)fv.size();
+    const int ns = __builtin_popcount(sel);
+    const uint32_t nb = t.bdep ? net.B : 1;
+    t.values.assign((size_t)nb << (ns + r), cd(1.0, 0.0));
+    std::vector<int> selbits;
+    for (int b = 0; b < 32; ++b)
+      if ((sel >> b) & 1u) selbits.push_back(b);
+    for (uint32_t bi = 0; bi < nb; ++bi)
+      for (uint32_t sv = 0; sv < (1u << ns); ++sv)
+        for (uint32_t e = 0; e < (1u << r); ++e) {
+          cd prod(1.0, 0.0);
+          for (int f : fs) {
+            const Factor &F = net.factors[f];
+            int idx = 0;
+            for (int j = 0; j < F.nv; ++j) {
+              int v = F.v[j], bit;
+              if (pos[v] >= 0) {
+                int k = (int)(std::find(fv.begin(), fv.end(), v) - fv.begin());
+                bit = (e >> (r - 1 - k)) & 1;
+              } else {
+                int k = (int)(std::find(selbits.begin(), selbits.end(), cutbit[v]) - selbits.begin());
+                bit = (sv >> k) & 1;
+              }
+              idx = idx * 2 + bit;
+            }
+            const auto &vals = net.values[f];
+            prod *= (F.kind == 2) ? vals[bi * 2 + idx] : vals[idx];
+          }
+          t.values[(((size_t)bi << ns) + sv) * ((size_t)1 << r) + e] = prod;
+        }
+    return add_tensor(std::move(t));
+  };
+
+  std::vector<int> leaf_of(V, -1);
+  for (int v : order)
+    if (!group[v].empty()) leaf_of[v] = make_leaf(group[v]);
+  int scalar_leaf = scalar_group.empty() ? -1 : make_leaf(scalar_group);
+
+  auto has = [](const Tensor &t, int v) {
+    return std::find(t.vars.begin(), t.vars.end(), v) != t.vars.end();
+  };
+  std::vector<int> pool, finals;
+  std::vector<char> done(V, 0);
+
+  auto emit = [&](std::vector<int> inputs, std::vector<int> kappa,
+                  std::vector<int> out) {
+    Step st;
+    std::sort(out.begin(), out.end(), by_pos);
+    Tensor c;
+    c.vars = out;
+    for (int i : inputs) {
+      c.bdep |= s.tensors[i].bdep;
+      c.sdep |= s.tensors[i].sdep;
+    }
+    const int stepno = (int)s.steps.size();
+    c.producer = stepno;
+    int cid = add_tensor(std::move(c));
+    st.out = cid;
+    st.in = inputs;
+    st.kappa = kappa;
+    st.rC = (int)out.size();
+    st.nk = (int)kappa.size();
+    st.bdep = s.tensors[cid].bdep;
+    st.sdep = s.tensors[cid].sdep;
+    std::vector<int> ivars(kappa);
+    ivars.insert(ivars.end(), out.begin(), out.end());
+    const int rI = (int)ivars.size();
+    if (rI > 31) throw std::runtime_error("step index space too large");
+    for (int i : inputs) {
+      const Tensor &t = s.tensors[i];
+      uint32_t m = 0;
+      size_t k = 0;
+      for (int j = 0; j < rI; ++j) {
+        if (has(t, ivars[j])) {
+          if (k >= t.vars.size() || t.vars[k] != ivars[j])
+            throw std::runtime_error("input layout is not a subsequence");
+          m |= 1u << (rI - 1 - j);
+          ++k;
+        }
+      }
+      if (k != t.vars.size()) throw std::runtime_error("input variable outside step");
+      st.mask.push_back(m);
+      s.tensors[i].last_use = stepno;
+    }
+    s.width = std::max(s.width, st.rC);
+    s.steps.push_back(st);
+    return cid;
+  };
+
+  auto union_vars = [&](const std::vector<int> &ins) {
+    std::vector<int> u;
+    for (int i : ins)
+      for (int v : s.tensors[i].vars)
+        if (std::find(u.begin(), u.end(), v) == u.end()) u.push_back(v);
+    std::sort(u.begin(), u.end(), by_pos);
+    return u;
+  };
+
+  for (size_t idx = 0; idx < order.size(); ++idx) {
+    const int v = order[idx];
+    if (done[v]) continue;
+    std::vector<int> inputs;
+    if (leaf_of[v] >= 0) inputs.push_back(leaf_of[v]);
+    std::vector<int> keep;
+    for (int t : pool) (has(s.tensors[t], v) ? inputs : keep).push_back(t);
+    pool.swap(keep);
+    done[v] = 1;
+    // Too many operands: multiply the two smallest first (v stays open).
+    while ((int)inputs.size() > kMaxIn) {
+      std::stable_sort(inputs.begin(), inputs.end(), [&](int a, int b) {
+        return s.tensors[a].rank() < s.tensors[b].rank();
+      });
+      std::vector<int> two{inputs[0], inputs[1]};
+      int pid = emit(two, {}, union_vars(two));
+      inputs.erase(inputs.begin(), inputs.begin() + 2);
+      inputs.push_back(pid);
+    }
+    std::vector<int> U = union_vars(inputs);
+    std::vector<int> kappa{v};
+    std::vector<int> out;
+    for (int u : U)
+      if (u != v) out.push_back(u);
+    // Chain fusion: a following bucket that holds only this result (and a
+    // leaf inside it) is summed in the same pass over the same index space.
+    if (o.fuse_chains) {
+      const int rI = (int)U.size();
+      while (idx + 1 < order.size()) {
+        const int w = order[idx + 1];
+        if (std::find(out.begin(), out.end(), w) == out.end()) break;
+        bool other = false;
+        for (int t : pool) other |= has(s.tensors[t], w);
+        if (other) break;
+        const int lw = leaf_of[w];
+        if (lw >= 0) {
+          if ((int)inputs.size() >= kMaxIn) break;
+          bool inside = true;
+          for (int u : s.tensors[lw].vars)
+            inside &= std::find(out.begin(), out.end(), u) != out.end();
+          if (!inside) break;
+        }
+        const int rC_after = (int)out.size() - 1;
+        if (!(rC_after >= 10 || rI <= 10)) break;
+        if ((int)kappa.size() >= 12) break;
+        kappa.push_back(w);
+        out.erase(std::find(out.begin(), out.end(), w));
+        if (lw >= 0) inputs.push_back(lw);
+        done[w] = 1;
+        ++idx;
+      }
+    }
+    int cid = emit(inputs, kappa, out);
+    if (s.tensors[cid].rank() == 0)
+      finals.push_back(cid);
+    else
+      pool.push_back(cid);
+  }
+  if (!pool.empty()) throw std::runtime_error("unfinished tensors after elimination");
+  if (scalar_leaf >= 0) finals.push_back(scalar_leaf);
+  if (finals.empty()) throw std::runtime_error("empty network");
+  while (finals.size() > 1 || s.tensors[finals[0]].leaf) {
+    std::vector<int> take(finals.begin(),
+                          finals.begin() + std::min<size_t>(finals.size(), kMaxIn));
+    std::vector<int> rest(finals.begin() + take.size(), finals.end());
+    int cid = emit(take, {}, {});
+    rest.insert(rest.begin(), cid);
+    finals.swap(rest);
+  }
+  s.result = finals[0];
+  s.tensors[s.result].last_use = (int)s.steps.size();  // read by the slice sum
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout: first-fit with liveness, per wave of S slices.
+// ---------------------------------------------------------------------------
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+int assign_storage(Schedule &s, int precision, double small_share) {
+  if (precision == 0) {
+    for (auto &t : s.tensors) t.f64 = true;
+    return 64;
+  }
+  // bytes moved per instance by tensors of each rank, stored as complex64
+  std::vector<double> by_rank(64, 0.0);
+  double total = 0.0;
+  for (const Step &st : s.steps) {
+    auto add = [&](int r) {
+      by_rank[r] += std::ldexp(8.0, r);
+      total += std::ldexp(8.0, r);
+    };
+    add(st.rC);
+    for (int i : st.in)
+      if (!s.tensors[i].leaf) add(s.tensors[i].rank());
+  }
+  int R = 0;
+  double acc = 0.0;
+  while (R < 63 && acc + by_rank[R] <= small_share * total) acc += by_rank[R++];
+  R = std::max(R, kAlwaysF64Rank);
+  for (auto &t : s.tensors) t.f64 = t.leaf || t.rank() < R;
+  return R;
+}
+
+Layout layout(Schedule &s, uint64_t B, uint64_t S) {
+  Layout L;
+  L.S = S;
+  std::vector<std::pair<uint64_t, uint64_t>> freel;  // (offset, size), sorted
+  uint64_t top = 0;
+  auto alloc = [&](uint64_t size) -> uint64_t {
+    for (size_t i = 0; i < freel.size(); ++i) {
+      if (freel[i].second >= size) {
+        uint64_t off = freel[i].first;
+        freel[i].first += size;
+        freel[i].second -= size;
+        if (freel[i].second == 0) freel.erase(freel.begin() + i);
+        return off;
+      }
+    }
+    uint64_t off = top;
+    top += size;
+    return off;
+  };
+  auto release = [&](uint64_t off, uint64_t size) {
+    auto it = std::lower_bound(freel.begin(), freel.end(), std::make_pair(off, uint64_t(0)));
+    it = freel.insert(it, {off, size});
+    size_t i = it - freel.begin();
+    if (i + 1 < freel.size() && freel[i].first + freel[i].second == freel[i + 1].first) {
+      freel[i].second += freel[i + 1].second;
+      freel.erase(freel.begin() + i + 1);
+    }
+    if (i > 0 && freel[i - 1].first + freel[i - 1].second == freel[i].first) {
+      freel[i - 1].second += freel[i].second;
+      freel.erase(freel.begin() + i);
+    }
+    if (!freel.empty() && freel.back().first + freel.back().second == top) {
+      top = freel.back().first;
+      freel.pop_back();
+    }
+  };
+  auto bytes_of = [&](const Tensor &t) {
+    return align256(instances(t, B, S) * ((uint64_t)1 << t.rank()) * (uint64_t)elem_bytes(t));
+  };
+  uint64_t peak = 0;
+  for (size_t st = 0; st < s.steps.size(); ++st) {
+    Tensor &c = s.tensors[s.steps[st].out];
+    c.data_off = alloc(bytes_of(c));
+    peak = std::max(peak, top);
+    for (int i : s.steps[st].in) {
+      Tensor &t = s.tensors[i];
+      if (!t.leaf && t.last_use == (int)st) release(t.data_off, bytes_of(t));
+    }
+  }
+  L.data_bytes = align256(peak);
+  uint64_t eo = L.data_bytes;
+  for (auto &t : s.tensors) {
+    if (t.leaf) continue;
+    t.exp_off = eo;
+    eo += align256(instances(t, B, S) * 8);
+  }
+  L.exp_bytes = eo - L.data_bytes;
+  L.partial_off = eo;
+  L.total_bytes = align256(eo + B * 32);
+  return L;
+}
+
+Costs schedule_costs(const Schedule &s, uint64_t B, uint64_t S) {
+  // Per wave of S slices; slice-invariant steps are reported apart and
+  // amortised by the caller over the slices of one amplitude.
+  Costs c;
+  for (const Step &st : s.steps) {
+    const Tensor &o = s.tensors[st.out];
+    double q = (double)instances(o, B, S);
+    double pts = q * std::ldexp(1.0, st.nk + st.rC);
+    double fl = pts * (6.0 * (double)(st.in.size() - 1) + (st.nk > 0 ? 2.0 : 0.0));
+    double by = q * std::ldexp(1.0, st.rC) * elem_bytes(o);
+    for (int i : st.in) {
+      const Tensor &t = s.tensors[i];
+      double qi = t.leaf ? (double)((t.bdep ? B : 1) *
+                                    std::min<uint64_t>(S, (uint64_t)1 << __builtin_popcount(t.selmask)))
+                         : (double)instances(t, B, S);
+      by += qi * std::ldexp(1.0, t.rank()) * elem_bytes(t);
+    }
+    if (st.sdep) {
+      c.flops_per_slice += fl / (double)S;
+      c.bytes_per_slice += by / (double)S;
+    } else {
+      c.flops_hoisted += fl;
+      c.bytes_hoisted += by;
+    }
+  }
+  return c;
+}
+
+}  // namespace qtn

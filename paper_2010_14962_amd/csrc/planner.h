@@ -1,0 +1,164 @@
+// Host planner of the sliced QAOA contraction: network construction, line
+// graph, min-fill elimination order, cut search (Algorithm 1) and the batched
+// contraction schedule shared by every slice.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace qtn {
+
+using cd = std::complex<double>;
+
+constexpr int kMaxIn = 8;        // inputs of one fused contraction step
+constexpr int kLeafMaxRank = 12; // largest merged leaf group
+constexpr int kAlwaysF64Rank = 8; // intermediates below this rank stay complex128
+
+// One gate factor of the merged binary network (Sec. II A, Fig. 1).
+struct Factor {
+  int nv;      // 1 or 2 variables
+  int v[2];    // variable ids, axis order of the values
+  int kind;    // 0 ZZ, 1 RX between layers, 2 measured RX (depends on x)
+  int layer;
+  int qubit;   // RX / OUT qubit
+};
+
+struct Network {
+  uint32_t n = 0, p = 0, nv = 0;
+  std::vector<std::pair<uint32_t, uint32_t>> edges;
+  std::vector<double> gamma, beta;
+  std::vector<uint8_t> bits;  // [B][n]
+  uint32_t B = 0;
+  std::vector<Factor> factors;
+  double prefactor = 1.0;     // 2^{-n/2} times the normalisations below
+  // normalised factor values; OUT factors hold one value pair per bitstring
+  std::vector<std::vector<cd>> values;  // [factor][B or 1][2^nv]
+};
+
+// Build factors, values and the normalisation prefactor.
+void build_network(Network &net);
+
+// Line graph (variable interaction graph), Sec. II B; adjacency lists sorted.
+std::vector<std::vector<int>> line_graph(const Network &net);
+
+struct EliminationResult {
+  std::vector<int> order;                 // free variables in elimination order
+  std::vector<std::vector<int>> nplus;    // neighbours at elimination, ascending
+  int width = 0;                          // max |N+(v)|
+  uint64_t work = 0;                      // sum 2^(|N+(v)|+1)
+};
+
+// Greedy min-fill on the line graph minus `removed`; ties (fill, degree, id).
+EliminationResult min_fill(const std::vector<std::vector<int>> &adj,
+                           const std::vector<int> &removed);
+
+// Counter-based SplitMix64 stream (Steele, Lea, Flood 2014).
+struct SplitMix64 {
+  uint64_t seed, counter = 0;
+  explicit SplitMix64(uint64_t s) : seed(s) {}
+  uint64_t next();
+  uint64_t below(uint64_t m) { return next() % m; }
+};
+
+struct CutResult {
+  std::vector<int> cut;  // ascending
+  int width = 0;
+  uint64_t work = 0;
+};
+
+// Algorithm 1 (Sec. III B) with exact min-fill fitness.
+CutResult ga_cut_search(const std::vector<std::vector<int>> &adj, int M, int N,
+                        int T, uint64_t seed);
+
+// ---------------------------------------------------------------------------
+// Schedule
+// ---------------------------------------------------------------------------
+
+struct Tensor {
+  std::vector<int> vars;   // ascending elimination position = MSB first
+  int rank() const { return (int)vars.size(); }
+  bool leaf = false;
+  bool bdep = false;       // depends on the bitstring
+  bool sdep = false;       // depends on the slice
+  bool f64 = true;         // intermediates: stored as complex128 (else complex64)
+  uint32_t selmask = 0;    // leaves: slice bits selecting the variant
+  std::vector<cd> values;  // leaves: [B or 1][2^popcount(selmask)][2^rank]
+  int producer = -1, last_use = -1;
+  // workspace placement (intermediates), set by layout()
+  uint64_t data_off = 0;   // byte offset of the data block
+  uint64_t exp_off = 0;    // byte offset of the exponent block
+  // leaves: element offset in the leaf buffer
+  uint64_t leaf_off = 0;
+};
+
+struct Step {
+  int out = -1;
+  std::vector<int> in;
+  std::vector<int> kappa;  // summed variables, MSB first
+  int rC = 0, nk = 0;
+  std::vector<uint32_t> mask;  // per input, over the nk + rC step-index bits
+  bool bdep = false, sdep = false;
+  int cls = 0;             // 0 E (streaming), 1 G (dense)
+};
+
+struct Schedule {
+  std::vector<Tensor> tensors;
+  std::vector<Step> steps;
+  int result = -1;         // rank-0 tensor holding each slice's value
+  int width = 0;           // largest intermediate rank
+};
+
+struct PlanOpts {
+  int precision = 0;
+  bool fuse_chains = true;
+};
+
+Schedule build_schedule(const Network &net, const std::vector<int> &cut,
+                        const std::vector<int> &order, const PlanOpts &o);
+
+// Host index tables of one step input (bit-exact integer maps).
+struct InputTables {
+  uint32_t lo[256];   // pext(c & 255, cmask & 255)
+  uint32_t mid[16];   // pext(((c >> 8) & 15) << 8, cmask)
+  uint32_t hi_mask;   // cmask >> 12
+  uint32_t hi_shift;  // popcount(cmask & 4095)
+  std::vector<uint32_t> kap;  // pext(kappa, kmask) << popcount(cmask)
+};
+uint32_t pext32(uint32_t x, uint32_t mask);
+InputTables input_tables(uint32_t mask, int rC, int nk);
+
+struct Layout {
+  uint64_t S = 1;                // slices per wave
+  uint64_t data_bytes = 0;       // intermediates region
+  uint64_t exp_bytes = 0;        // exponents region
+  uint64_t total_bytes = 0;
+  uint64_t partial_off = 0;      // running per-bitstring partials
+};
+
+// Instance count of a tensor inside a wave.
+inline uint64_t instances(const Tensor &t, uint64_t B, uint64_t S) {
+  return (t.bdep ? B : 1) * (t.sdep ? S : 1);
+}
+
+// Storage precision of every intermediate.  FP64 plans store everything as
+// complex128.  Mixed plans store the large tensors, which carry the HBM
+// traffic, as complex64 and keep the small ones (at most `small_share` of the
+// complex64 bytes) as complex128.  Returns the rank below which tensors stay
+// complex128.
+int assign_storage(Schedule &s, int precision, double small_share = 0.03);
+
+inline int elem_bytes(const Tensor &t) { return t.f64 ? 16 : 8; }
+
+Layout layout(Schedule &s, uint64_t B, uint64_t S);
+
+struct Costs {
+  double flops_per_slice = 0;    // all bitstrings
+  double bytes_per_slice = 0;
+  double flops_hoisted = 0;      // slice-invariant steps, once per wave
+  double bytes_hoisted = 0;
+};
+Costs schedule_costs(const Schedule &s, uint64_t B, uint64_t S);
+
+}  // namespace qtn

@@ -1,0 +1,264 @@
+"""ctypes binding of libqtn (argument marshalling only).
+
+Every step of the contraction runs in libqtn's HIP kernels; this module only
+converts Python/NumPy arguments, hands over device pointers and HIP streams
+(PyTorch supplies device memory and streams), and raises on error codes.  If
+libqtn.so is missing the import of any entry point raises: there is no other
+execution path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int32, c_uint32, c_uint64, c_uint8, c_void_p
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqtn.so")
+
+QTN_OK, QTN_EINVAL, QTN_ERANGE, QTN_ERANK, QTN_ENOMEM, QTN_EHIP, QTN_ESTATE = 0, -1, -2, -3, -4, -5, -6
+QTN_FP64, QTN_FP32, QTN_3XBF16 = 0, 1, 2
+PRECISIONS = {"fp64": QTN_FP64, "fp32": QTN_FP32, "3xbf16": QTN_3XBF16}
+STEP_REC, TENSOR_REC = 24, 40
+
+
+class QtnGraph(ctypes.Structure):
+    _fields_ = [("n", c_uint32), ("m", c_uint32), ("edges", POINTER(c_uint32))]
+
+
+class QtnPlanOpts(ctypes.Structure):
+    _fields_ = [("k", c_int32), ("max_rank", c_int32), ("k_max", c_int32),
+                ("cut_vars", POINTER(c_uint32)), ("seed", c_uint64),
+                ("ga_pop", c_int32), ("ga_iters", c_int32), ("precision", c_int32),
+                ("fuse_chains", c_int32)]
+
+
+class QtnPartial(ctypes.Structure):
+    _fields_ = [("re", c_double), ("im", c_double), ("re_comp", c_double), ("im_comp", c_double)]
+
+    def value(self) -> complex:
+        return complex(self.re + self.re_comp, self.im + self.im_comp)
+
+
+class QtnPlanInfo(ctypes.Structure):
+    _fields_ = [("n", c_uint32), ("p", c_uint32), ("n_vars", c_uint32), ("n_bitstrings", c_uint32),
+                ("k", c_int32), ("width", c_int32), ("n_steps", c_int32), ("n_tensors", c_int32),
+                ("log2_flops", c_double), ("bytes_per_slice", c_double),
+                ("flops_hoisted", c_double), ("work", c_double), ("prefactor", c_double),
+                ("search_seconds", c_double), ("precision", c_int32),
+                ("f64_below_rank", c_int32)]
+
+
+class QtnKernelTiming(ctypes.Structure):
+    _fields_ = [("launches", c_uint64), ("total_ms", c_double), ("alg_bytes", c_double),
+                ("alg_flops", c_double)]
+
+
+class QtnError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("qtn error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_query",
+           "qtn_plan_cut", "qtn_plan_order", "qtn_plan_export", "qtn_plan_kappa",
+           "qtn_plan_index_table", "qtn_plan_leaf_values", "qtn_plan_workspace_bytes",
+           "qtn_plan_bind_workspace", "qtn_contract", "qtn_partial_combine",
+           "qtn_plan_set_timing", "qtn_plan_timing", "qtn_last_error"]
+
+
+def lib():
+    """Loads libqtn.so (built in-tree by paper_2010_14962_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libqtn.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    L.qtn_plan_opts_default.argtypes = [POINTER(QtnPlanOpts)]
+    L.qtn_plan_opts_default.restype = None
+    L.qtn_plan.argtypes = [POINTER(QtnGraph), c_uint32, POINTER(c_double), POINTER(c_double),
+                           POINTER(c_uint8), c_uint32, POINTER(QtnPlanOpts), POINTER(c_void_p)]
+    L.qtn_plan_destroy.argtypes = [c_void_p]
+    L.qtn_plan_destroy.restype = None
+    L.qtn_plan_query.argtypes = [c_void_p, POINTER(QtnPlanInfo)]
+    L.qtn_plan_cut.argtypes = [c_void_p, POINTER(c_uint32), c_uint32]
+    L.qtn_plan_order.argtypes = [c_void_p, POINTER(c_uint32), c_uint32]
+    L.qtn_plan_export.argtypes = [c_void_p, POINTER(c_int32), c_uint32, POINTER(c_int32), c_uint32]
+    L.qtn_plan_kappa.argtypes = [c_void_p, c_int32, POINTER(c_int32), c_uint32]
+    L.qtn_plan_index_table.argtypes = [c_void_p, c_int32, c_int32, POINTER(c_uint32), c_uint32,
+                                       POINTER(c_uint32)]
+    L.qtn_plan_leaf_values.argtypes = [c_void_p, c_int32, POINTER(c_double), c_uint64,
+                                       POINTER(c_uint64)]
+    L.qtn_plan_workspace_bytes.argtypes = [c_void_p, c_uint64, POINTER(c_uint64)]
+    L.qtn_plan_bind_workspace.argtypes = [c_void_p, c_void_p, c_uint64, c_uint64]
+    L.qtn_contract.argtypes = [c_void_p, c_uint64, c_uint64, c_void_p, POINTER(QtnPartial)]
+    L.qtn_partial_combine.argtypes = [POINTER(QtnPartial), POINTER(QtnPartial), POINTER(QtnPartial)]
+    L.qtn_plan_set_timing.argtypes = [c_void_p, c_int32]
+    L.qtn_plan_timing.argtypes = [c_void_p, POINTER(QtnKernelTiming)]
+    L.qtn_last_error.argtypes = []
+    L.qtn_last_error.restype = c_char_p
+    for name in EXPORTS:
+        if name not in ("qtn_plan_opts_default", "qtn_plan_destroy", "qtn_last_error"):
+            getattr(L, name).restype = c_int32
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != QTN_OK:
+        raise QtnError(rc, lib().qtn_last_error().decode())
+
+
+def _u32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint32))
+
+
+class Plan:
+    """Owns one qtn_plan_t handle (and, once bound, a torch workspace)."""
+
+    def __init__(self, handle: int, n: int, n_bitstrings: int):
+        self._h = c_void_p(handle)
+        self.n = n
+        self.n_bitstrings = n_bitstrings
+        self._workspace = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().qtn_plan_destroy(self._h)
+        self._h = None
+
+    # queries --------------------------------------------------------------
+    def info(self) -> dict:
+        inf = QtnPlanInfo()
+        _check(lib().qtn_plan_query(self._h, byref(inf)))
+        return {f: getattr(inf, f) for f, _ in QtnPlanInfo._fields_}
+
+    def cut(self) -> List[int]:
+        k = self.info()["k"]
+        buf = (c_uint32 * max(k, 1))()
+        _check(lib().qtn_plan_cut(self._h, buf, k))
+        return [int(buf[i]) for i in range(k)]
+
+    def order(self) -> List[int]:
+        inf = self.info()
+        m = inf["n_vars"] - inf["k"]
+        buf = (c_uint32 * max(m, 1))()
+        _check(lib().qtn_plan_order(self._h, buf, m))
+        return [int(buf[i]) for i in range(m)]
+
+    def export(self):
+        inf = self.info()
+        ns, nt = inf["n_steps"], inf["n_tensors"]
+        steps = np.zeros((ns, STEP_REC), dtype=np.int32)
+        tens = np.zeros((nt, TENSOR_REC), dtype=np.int32)
+        _check(lib().qtn_plan_export(self._h, steps.ctypes.data_as(POINTER(c_int32)), ns,
+                                     tens.ctypes.data_as(POINTER(c_int32)), nt))
+        return steps, tens
+
+    def kappa(self, step: int) -> List[int]:
+        buf = (c_int32 * 64)()
+        _check(lib().qtn_plan_kappa(self._h, step, buf, 64))
+        steps, _ = self.export()
+        return [int(buf[i]) for i in range(int(steps[step, 2]))]
+
+    def index_table(self, step: int, inp: int) -> np.ndarray:
+        cnt = c_uint32(0)
+        _check(lib().qtn_plan_index_table(self._h, step, inp, None, 0, byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.uint32)
+        _check(lib().qtn_plan_index_table(self._h, step, inp, out.ctypes.data_as(POINTER(c_uint32)),
+                                          cnt.value, byref(cnt)))
+        return out
+
+    def leaf_values(self, tensor: int) -> np.ndarray:
+        cnt = c_uint64(0)
+        _check(lib().qtn_plan_leaf_values(self._h, tensor, None, 0, byref(cnt)))
+        out = np.zeros(2 * cnt.value, dtype=np.float64)
+        _check(lib().qtn_plan_leaf_values(self._h, tensor, out.ctypes.data_as(POINTER(c_double)),
+                                          cnt.value, byref(cnt)))
+        return out[0::2] + 1j * out[1::2]
+
+    def workspace_bytes(self, slices_per_wave: int) -> int:
+        b = c_uint64(0)
+        _check(lib().qtn_plan_workspace_bytes(self._h, slices_per_wave, byref(b)))
+        return int(b.value)
+
+    # device ---------------------------------------------------------------
+    def bind_workspace(self, device_ptr: int, nbytes: int, slices_per_wave: int):
+        _check(lib().qtn_plan_bind_workspace(self._h, c_void_p(device_ptr), nbytes, slices_per_wave))
+
+    def bind_torch(self, slices_per_wave: int, device=None):
+        """Allocates the workspace as a torch uint8 tensor on `device` and binds it."""
+        import torch
+        nbytes = self.workspace_bytes(slices_per_wave)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+        self.bind_workspace(ws.data_ptr(), nbytes, slices_per_wave)
+        self._workspace = ws
+        return ws
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().qtn_plan_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        t = QtnKernelTiming()
+        _check(lib().qtn_plan_timing(self._h, byref(t)))
+        return {f: getattr(t, f) for f, _ in QtnKernelTiming._fields_}
+
+    def contract(self, slice_lo: int, slice_hi: int, stream: Optional[int] = None) -> List[QtnPartial]:
+        out = (QtnPartial * self.n_bitstrings)()
+        _check(lib().qtn_contract(self._h, slice_lo, slice_hi, c_void_p(stream or 0), out))
+        return [out[i] for i in range(self.n_bitstrings)]
+
+
+def qtn_plan(n: int, edges: Sequence, p: int, gamma: Sequence[float], beta: Sequence[float],
+             bitstrings, k: int = -1, max_rank: int = 0, k_max: int = 24,
+             cut_vars: Optional[Sequence[int]] = None, seed: int = 0, ga_pop: int = 11,
+             ga_iters: int = 4, precision: str = "fp64", fuse_chains: bool = True) -> Plan:
+    """Builds a plan (host only): network, cut set, order and schedule."""
+    L = lib()
+    e = _u32(edges).reshape(-1)
+    g = QtnGraph(n, len(e) // 2, e.ctypes.data_as(POINTER(c_uint32)))
+    bits = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint8).reshape(-1, n))
+    ga = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64))
+    be = np.ascontiguousarray(np.asarray(beta, dtype=np.float64))
+    opts = QtnPlanOpts()
+    L.qtn_plan_opts_default(byref(opts))
+    opts.k = k
+    opts.max_rank = max_rank
+    opts.k_max = k_max
+    opts.seed = seed
+    opts.ga_pop = ga_pop
+    opts.ga_iters = ga_iters
+    opts.precision = PRECISIONS[precision]
+    opts.fuse_chains = 1 if fuse_chains else 0
+    cv = None
+    if cut_vars is not None:
+        cv = _u32(cut_vars)
+        opts.k = len(cv)
+        opts.cut_vars = cv.ctypes.data_as(POINTER(c_uint32))
+    h = c_void_p()
+    _check(L.qtn_plan(byref(g), p, ga.ctypes.data_as(POINTER(c_double)),
+                      be.ctypes.data_as(POINTER(c_double)), bits.ctypes.data_as(POINTER(c_uint8)),
+                      bits.shape[0], byref(opts), byref(h)))
+    return Plan(h.value, n, bits.shape[0])
+
+
+def qtn_partial_combine(a: QtnPartial, b: QtnPartial) -> QtnPartial:
+    out = QtnPartial()
+    _check(lib().qtn_partial_combine(byref(a), byref(b), byref(out)))
+    return out
+
+
+def plan_instance(inst, **kw) -> Plan:
+    """qtn_plan for an instances.Instance."""
+    return qtn_plan(inst.n, inst.edges, inst.p, inst.gamma, inst.beta, inst.bitstrings, **kw)

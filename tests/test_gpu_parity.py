@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tolerances: FP64 path 1e-12 relative; FP32 path (with per-slice power-of-two
+rescaling) 1e-6 relative, as required for the single-precision form.  The
+relative error of an amplitude a against the oracle value r is |a-r|/|r|;
+when |r| < 1e-6 * 2^{-n/2} (a near-cancelling amplitude) the denominator is
+2^{-n/2} instead.  Per-slice values are compared relative to the largest
+slice value of the same bitstring.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from instances import make_instance, workload_instance
+from oracle import qaoa as Q
+from paper_2010_14962_amd import plan_instance, qtn
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _rel(a, r, n):
+    den = abs(r) if abs(r) >= 1e-6 * 2.0 ** (-n / 2) else 2.0 ** (-n / 2)
+    return abs(a - r) / den
+
+
+def _amps(plan, lo, hi):
+    return [p.value() for p in plan.contract(lo, hi, _stream())]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("S", [1, 3, 4])
+def test_tiny_sliced_all_slices(precision, S):
+    print("case n16 p1 k2", precision, "S", S, flush=True)
+    inst = workload_instance("qaoa_n16_p1_k2", seed=0)
+    plan = plan_instance(inst, k=2, precision=precision)
+    plan.bind_torch(S)
+    cut = plan.cut()
+    x = inst.bitstrings[0]
+    parts = [Q.slice_partial(16, inst.edges, 1, inst.gamma, inst.beta, x, cut, s) for s in range(4)]
+    scale = max(abs(p) for p in parts)
+    for s in range(4):
+        got = _amps(plan, s, s + 1)[0]
+        assert abs(got - parts[s]) <= TOL[precision] * scale, (s, got, parts[s])
+    full = _amps(plan, 0, 4)[0]
+    sv = Q.statevector_amplitude(16, inst.edges, 1, inst.gamma, inst.beta, x)
+    assert _rel(full, sv, 16) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_zero_angles_exact(precision):
+    inst = make_instance(16, 1, 3, 4)
+    plan = qtn.qtn_plan(16, inst.edges, 1, [0.0], [0.0], inst.bitstrings, k=2, precision=precision)
+    plan.bind_torch(4)
+    for a in _amps(plan, 0, 4):
+        assert a == complex(2.0 ** -8, 0.0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_closed_form_gamma0(precision):
+    inst = make_instance(20, 2, 2, 5)
+    plan = qtn.qtn_plan(20, inst.edges, 2, [0.0, 0.0], inst.beta, inst.bitstrings, k=3,
+                        precision=precision)
+    plan.bind_torch(8)
+    for b, a in enumerate(_amps(plan, 0, 8)):
+        ref = Q.closed_form_amplitude(20, inst.edges, 2, [0.0, 0.0], inst.beta, inst.bitstrings[b])
+        assert _rel(a, ref, 20) <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_n40_p2_b32_k8_all_amplitudes(precision):
+    """32 bitstrings x 256 slices; the slice sum equals the uncut oracle
+    contraction (Eq. (2))."""
+    print("case n40 p2 b32 k8", precision, flush=True)
+    inst = workload_instance("qaoa_n40_p2_b32_k8", seed=0)
+    plan = plan_instance(inst, k=8, max_rank=18, precision=precision)
+    plan.bind_torch(100)   # 256 slices in waves of 100: ragged last wave
+    amps = _amps(plan, 0, 256)
+    order = plan_instance(inst, k=0).order()
+    worst = 0.0
+    for b in range(32):
+        ref = Q.ve_amplitude(40, inst.edges, 2, inst.gamma, inst.beta, inst.bitstrings[b], order=order)
+        worst = max(worst, _rel(amps[b], ref, 40))
+    print("worst rel err", worst)
+    assert worst <= TOL[precision]
+    # per-slice values of one bitstring on a sample of slices
+    cut = plan.cut()
+    for s in (0, 77, 255):
+        part = Q.slice_partial(40, inst.edges, 2, inst.gamma, inst.beta, inst.bitstrings[3], cut, s)
+        got = _amps(plan, s, s + 1)[3]
+        assert abs(got - part) <= TOL[precision] * max(abs(part), 2.0 ** -20 * 2 ** -4)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_n120_p1_b8(precision):
+    """The 120-qubit, depth-1 workload: k is the smallest cut size whose
+    searched cut keeps every slice tensor at rank <= 26."""
+    print("case n120 p1 b8", precision, flush=True)
+    inst = workload_instance("qaoa_n120_p1_b8", seed=0)
+    plan = plan_instance(inst, k=-1, max_rank=26, precision=precision)
+    k = plan.info()["k"]
+    plan.bind_torch(1 << min(k, 4))
+    amps = _amps(plan, 0, 1 << k)
+    cut = plan.cut()
+    order = plan.order()
+    for b in (0, 5):
+        x = inst.bitstrings[b]
+        if k == 0:
+            ref = Q.ve_amplitude(120, inst.edges, 1, inst.gamma, inst.beta, x, order=order)
+        else:
+            ref = Q.sliced_amplitude(120, inst.edges, 1, inst.gamma, inst.beta, x, cut, order=order)
+        assert _rel(amps[b], ref, 120) <= TOL[precision], (b, amps[b], ref)
+    # complement symmetry holds at any size: amp(x) = amp(not x)
+    bits = np.concatenate([inst.bitstrings[:2], 1 - inst.bitstrings[:2]])
+    p2 = qtn.qtn_plan(120, inst.edges, 1, inst.gamma, inst.beta, bits, cut_vars=cut,
+                      precision=precision)
+    p2.bind_torch(1)
+    a2 = _amps(p2, 0, 1 << k)
+    for b in range(2):
+        assert _rel(a2[b], a2[b + 2], 120) <= TOL[precision]
+
+
+def test_n80_p2_k16_slice_subset():
+    """65536 identical-structure slices; a subset of slices against the
+    oracle and a 1024-slice range in FP32 against FP64 on the GPU."""
+    print("case n80 p2 k16", flush=True)
+    inst = workload_instance("qaoa_n80_p2_k16", seed=0)
+    p64 = plan_instance(inst, k=16, max_rank=24, precision="fp64", ga_pop=32, ga_iters=20)
+    cut = p64.cut()
+    p32 = plan_instance(inst, cut_vars=cut, precision="fp32")
+    p64.bind_torch(256)
+    p32.bind_torch(256)
+    x = inst.bitstrings[0]
+    order = p64.order()
+    for s in (0, 1, 4095, 65535):
+        part = Q.slice_partial(80, inst.edges, 2, inst.gamma, inst.beta, x, cut, s, order=order)
+        g64 = _amps(p64, s, s + 1)[0]
+        g32 = _amps(p32, s, s + 1)[0]
+        assert abs(g64 - part) <= 1e-12 * abs(part) + 1e-300
+        assert abs(g32 - part) <= 1e-6 * abs(part) + 1e-300
+    a64 = _amps(p64, 0, 1024)[0]
+    a32 = _amps(p32, 0, 1024)[0]
+    assert abs(a32 - a64) <= 1e-6 * abs(a64)
+
+
+def test_ranges_combine_and_determinism():
+    inst = workload_instance("qaoa_n40_p2_b32_k8", seed=1)
+    plan = plan_instance(inst, k=8, precision="fp32")
+    plan.bind_torch(64)
+    whole = plan.contract(0, 256, _stream())
+    again = plan.contract(0, 256, _stream())
+    for a, b in zip(whole, again):
+        assert (a.re, a.im, a.re_comp, a.im_comp) == (b.re, b.im, b.re_comp, b.im_comp)
+    left = plan.contract(0, 100, _stream())
+    right = plan.contract(100, 256, _stream())
+    for w, l, r in zip(whole, left, right):
+        c = qtn.qtn_partial_combine(l, r)
+        assert abs(c.value() - w.value()) <= 1e-6 * abs(w.value())
+
+
+def test_degenerate_all_variables_cut():
+    inst = make_instance(6, 1, 2, 7)
+    plan = plan_instance(inst, cut_vars=list(range(6)), precision="fp64")
+    plan.bind_torch(64)
+    amps = _amps(plan, 0, 64)
+    for b in range(2):
+        sv = Q.statevector_amplitude(6, inst.edges, 1, inst.gamma, inst.beta, inst.bitstrings[b])
+        assert _rel(amps[b], sv, 6) <= 1e-12
+    assert [p.value() for p in plan.contract(5, 5)] == [0j, 0j]
