@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices-per-wave", type=int, default=4096)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the sliced contraction shards by slice range "
@@ -97,6 +99,14 @@ def main():
     from paper_2010_14962_amd import plan_instance, qtn_plan
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# copy calibration: %d bytes read, %d bytes written" % (n, n), file=sys.stderr, flush=True)
+        del src, dst
     inst = workload_instance(args.workload, seed=args.seed)
     w = inst.meta
     t0 = time.perf_counter()

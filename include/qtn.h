@@ -82,6 +82,7 @@ typedef struct {
   int32_t ga_iters;          /* T of Algorithm 1 (default 4)                               */
   int32_t precision;         /* QTN_FP64, QTN_FP32 or QTN_3XBF16                           */
   int32_t fuse_chains;       /* 1: sum chains of trivial buckets in one step (default 1)   */
+  int32_t exec_mode;         /* -1 auto, 0 grid-wide steps, 1 one workgroup per instance  */
 } qtn_plan_opts;
 
 typedef struct {
@@ -98,10 +99,15 @@ typedef struct {
   double search_seconds;     /* time spent in the cut search                              */
   int32_t precision;
   int32_t f64_below_rank;    /* intermediates of smaller rank are stored as complex128    */
+  int32_t n_programs_wide;   /* workgroup programs (trees of small steps), grid-wide mode */
+  int32_t n_launches_wide;   /* kernel launches per wave, grid-wide mode                  */
+  uint32_t slice_lds_bytes;  /* LDS per workgroup, one-workgroup-per-instance mode        */
+  double slice_scratch_bytes;/* global scratch per workgroup, same mode                   */
 } qtn_plan_info;
 
 /* Fills defaults: k = -1, max_rank = 0, k_max = 24, cut_vars = NULL, seed = 0,
- * ga_pop = 11, ga_iters = 4 (Sec. IV A), precision = QTN_FP64, fuse_chains = 1. */
+ * ga_pop = 11, ga_iters = 4 (Sec. IV A), precision = QTN_FP64, fuse_chains = 1,
+ * exec_mode = -1. */
 void qtn_plan_opts_default(qtn_plan_opts *opts);
 
 /*

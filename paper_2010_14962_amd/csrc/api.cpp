@@ -31,6 +31,7 @@ extern "C" void qtn_plan_opts_default(qtn_plan_opts *o) {
   o->ga_iters = 4;  // Sec. IV A: 4 iterations
   o->precision = QTN_FP64;
   o->fuse_chains = 1;
+  o->exec_mode = -1;
 }
 
 static int fail(int code, const std::string &msg) {
@@ -142,6 +143,9 @@ extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
     P->popts.fuse_chains = opts.fuse_chains != 0;
     P->sched = build_schedule(net, P->cut, P->order, P->popts);
     P->f64_below_rank = assign_storage(P->sched, P->precision);
+    P->exec_mode = opts.exec_mode;
+    P->exec[MODE_WIDE] = build_exec(P->sched, MODE_WIDE, kLdsBudget);
+    P->exec[MODE_SLICE] = build_exec(P->sched, MODE_SLICE, kLdsBudget);
     if (opts.max_rank > 0 && P->sched.width > opts.max_rank) {
       delete P;
       return fail(QTN_ERANK, "cut set does not meet max_rank");
@@ -185,6 +189,10 @@ extern "C" int qtn_plan_query(const qtn_plan_t *P, qtn_plan_info *info) {
   info->search_seconds = P->search_seconds;
   info->precision = P->precision;
   info->f64_below_rank = P->f64_below_rank;
+  info->n_programs_wide = (int32_t)P->exec[MODE_WIDE].programs.size();
+  info->n_launches_wide = (int32_t)P->exec[MODE_WIDE].launches.size();
+  info->slice_lds_bytes = P->exec[MODE_SLICE].lds_bytes;
+  info->slice_scratch_bytes = (double)P->exec[MODE_SLICE].scratch_per_wg;
   return QTN_OK;
 }
 
@@ -286,12 +294,40 @@ extern "C" int qtn_plan_leaf_values(const qtn_plan_t *P, int32_t tensor, double 
   return QTN_OK;
 }
 
+namespace qtn {
+uint64_t wg_slots_for(const qtn_plan_t *P, int mode, uint64_t S) {
+  if (mode != MODE_SLICE) return 0;
+  const Program &pr = P->exec[MODE_SLICE].programs[0];
+  const uint64_t items = (pr.bdep ? P->net.B : 1) * (pr.sdep ? S : 1);
+  return std::min<uint64_t>(items, kMaxWorkgroups);
+}
+
+int choose_mode(const qtn_plan_t *P, uint64_t S) {
+  if (P->exec_mode == MODE_WIDE || P->exec_mode == MODE_SLICE) return P->exec_mode;
+  const uint64_t items = (uint64_t)P->net.B * S;
+  const uint64_t slots = std::min<uint64_t>(items, kMaxWorkgroups);
+  const uint64_t scratch = slots * P->exec[MODE_SLICE].scratch_per_wg;
+  return (items >= 512 && scratch <= kMaxScratchTotal) ? MODE_SLICE : MODE_WIDE;
+}
+}  // namespace qtn
+
+static uint64_t clamp_S(const qtn_plan_t *P, uint64_t S) {
+  const uint64_t maxS = P->cut.empty() ? 1 : (1ull << P->cut.size());
+  return std::min(S, maxS);
+}
+
 extern "C" int qtn_plan_workspace_bytes(const qtn_plan_t *P, uint64_t S, uint64_t *bytes) {
   if (!P || !bytes) return fail(QTN_EINVAL, "NULL argument");
   if (S == 0) return fail(QTN_EINVAL, "slices_per_wave must be >= 1");
+  S = clamp_S(P, S);
+  const int mode = choose_mode(P, S);
   Schedule copy = P->sched;
-  Layout L = layout(copy, P->net.B, S);
-  *bytes = L.total_bytes;
+  try {
+    Layout L = layout(copy, P->exec[mode], P->net.B, S, wg_slots_for(P, mode, S));
+    *bytes = L.total_bytes;
+  } catch (const std::exception &e) {
+    return fail(QTN_ESTATE, e.what());
+  }
   return QTN_OK;
 }
 

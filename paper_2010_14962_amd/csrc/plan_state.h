@@ -8,6 +8,14 @@
 
 namespace qtn {
 struct DeviceState;  // defined by the HIP runtime
+constexpr uint32_t kLdsBudget = 56 * 1024;   // LDS bytes for program tensors
+constexpr uint64_t kMaxWorkgroups = 1024;    // persistent workgroups of a program launch
+constexpr uint64_t kMaxScratchTotal = 64ull << 30;
+// Execution mode for `slices_per_wave` slices: one workgroup per instance
+// (MODE_SLICE) when there are enough instances to fill the chip and their
+// scratch fits, else grid-wide streaming steps (MODE_WIDE).
+int choose_mode(const struct qtn_plan_s *P, uint64_t S);
+uint64_t wg_slots_for(const struct qtn_plan_s *P, int mode, uint64_t S);
 void device_state_free(DeviceState *d);
 void set_error(const std::string &msg);
 }  // namespace qtn
@@ -23,5 +31,7 @@ struct qtn_plan_s {
   uint64_t work = 0;       // sum 2^(|N+(v)|+1)
   double search_seconds = 0.0;
   int f64_below_rank = 0;  // intermediates of smaller rank are stored as complex128
+  int exec_mode = -1;      // -1 chosen per binding, else qtn::ExecMode
+  qtn::ExecPlan exec[2];   // MODE_WIDE, MODE_SLICE
   qtn::DeviceState *dev = nullptr;
 };

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <stdexcept>
@@ -469,9 +470,15 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
             inside &= std::find(out.begin(), out.end(), u) != out.end();
           if (!inside) break;
         }
+        // Small index spaces are summed in one workgroup and may fuse freely;
+        // streaming steps keep enough outputs to fill the chip and sum at
+        // most kMaxStreamKappa variables per pass.
         const int rC_after = (int)out.size() - 1;
-        if (!(rC_after >= 10 || rI <= 10)) break;
-        if ((int)kappa.size() >= 12) break;
+        if (rI <= kSmallRank) {
+          if ((int)kappa.size() >= 12) break;
+        } else {
+          if (rC_after < kSmallRank || (int)kappa.size() >= kMaxStreamKappa) break;
+        }
         kappa.push_back(w);
         out.erase(std::find(out.begin(), out.end(), w));
         if (lw >= 0) inputs.push_back(lw);
@@ -504,7 +511,6 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
 // ---------------------------------------------------------------------------
 // Workspace layout: first-fit with liveness, per wave of S slices.
 // ---------------------------------------------------------------------------
-static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 int assign_storage(Schedule &s, int precision, double small_share) {
   if (precision == 0) {
@@ -531,26 +537,31 @@ int assign_storage(Schedule &s, int precision, double small_share) {
   return R;
 }
 
-Layout layout(Schedule &s, uint64_t B, uint64_t S) {
-  Layout L;
-  L.S = S;
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+namespace {
+// First-fit interval allocator over a linear address space.
+struct FirstFit {
   std::vector<std::pair<uint64_t, uint64_t>> freel;  // (offset, size), sorted
-  uint64_t top = 0;
-  auto alloc = [&](uint64_t size) -> uint64_t {
+  uint64_t top = 0, peak = 0;
+  uint64_t limit = ~uint64_t(0);
+  bool alloc(uint64_t size, uint64_t &off) {
     for (size_t i = 0; i < freel.size(); ++i) {
       if (freel[i].second >= size) {
-        uint64_t off = freel[i].first;
+        off = freel[i].first;
         freel[i].first += size;
         freel[i].second -= size;
         if (freel[i].second == 0) freel.erase(freel.begin() + i);
-        return off;
+        return true;
       }
     }
-    uint64_t off = top;
+    if (top + size > limit) return false;
+    off = top;
     top += size;
-    return off;
-  };
-  auto release = [&](uint64_t off, uint64_t size) {
+    peak = std::max(peak, top);
+    return true;
+  }
+  void release(uint64_t off, uint64_t size) {
     auto it = std::lower_bound(freel.begin(), freel.end(), std::make_pair(off, uint64_t(0)));
     it = freel.insert(it, {off, size});
     size_t i = it - freel.begin();
@@ -566,30 +577,239 @@ Layout layout(Schedule &s, uint64_t B, uint64_t S) {
       top = freel.back().first;
       freel.pop_back();
     }
+  }
+};
+}  // namespace
+
+ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget) {
+  const int nst = (int)s.steps.size();
+  const int nt = (int)s.tensors.size();
+  ExecPlan x;
+  x.mode = mode;
+  x.loc.assign(nt, LOC_GLOBAL);
+  x.off.assign(nt, 0);
+  x.slot.assign(nt, -1);
+  std::vector<int> consumer(nt, -1);
+  for (int st = 0; st < nst; ++st)
+    for (int i : s.steps[st].in) consumer[i] = st;
+  for (int t = 0; t < nt; ++t)
+    if (s.tensors[t].leaf) x.loc[t] = LOC_LEAF;
+
+  // Pack the tensors of one program: LDS first (complex128), else scratch
+  // (or the workspace in wide mode).  Returns false if nothing could be placed.
+  auto pack = [&](Program &P, bool scratch_ok) {
+    FirstFit lds, scr;
+    lds.limit = lds_budget;
+    std::vector<char> mine(nt, 0);
+    for (int st : P.steps) mine[s.steps[st].out] = 1;
+    int slots = 0;
+    for (int st : P.steps) {
+      const int o = s.steps[st].out;
+      if (o != P.root) {
+        const uint64_t lbytes = (uint64_t)16 << s.tensors[o].rank();
+        uint64_t off;
+        if (lds.alloc((lbytes + 15) & ~uint64_t(15), off)) {
+          x.loc[o] = LOC_LDS;
+          x.off[o] = off;
+        } else if (scratch_ok) {
+          const uint64_t sb = (((uint64_t)elem_bytes(s.tensors[o]) << s.tensors[o].rank()) + 255) & ~uint64_t(255);
+          scr.alloc(sb, off);
+          x.loc[o] = LOC_SCRATCH;
+          x.off[o] = off;
+        } else {
+          x.loc[o] = LOC_GLOBAL;
+        }
+        if (x.loc[o] != LOC_GLOBAL) x.slot[o] = slots++;
+      }
+      for (int i : s.steps[st].in) {
+        if (!mine[i] || consumer[i] != st) continue;
+        const Tensor &t = s.tensors[i];
+        if (x.loc[i] == LOC_LDS)
+          lds.release(x.off[i], (((uint64_t)16 << t.rank()) + 15) & ~uint64_t(15));
+        else if (x.loc[i] == LOC_SCRATCH)
+          scr.release(x.off[i], (((uint64_t)elem_bytes(t) << t.rank()) + 255) & ~uint64_t(255));
+      }
+    }
+    P.lds_bytes = (uint32_t)lds.peak;
+    P.scratch_bytes = scr.peak;
+    P.nslots = slots;
   };
+
+  if (mode == MODE_SLICE) {
+    Program P;
+    for (int st = 0; st < nst; ++st) P.steps.push_back(st);
+    P.root = s.result;
+    P.bdep = s.tensors[s.result].bdep;
+    P.sdep = s.tensors[s.result].sdep;
+    pack(P, true);
+    x.programs.push_back(P);
+    LaunchGroup g;
+    g.kind = 0;
+    g.programs.push_back(0);
+    x.launches.push_back(g);
+  } else {
+    std::vector<char> small(nst, 0);
+    for (int st = 0; st < nst; ++st) {
+      const Step &S_ = s.steps[st];
+      small[st] = S_.rC < kSmallRank && S_.rC + S_.nk <= kSmallRank + 4;
+    }
+    // components of small steps joined through small -> small edges
+    std::vector<int> parent(nst);
+    std::iota(parent.begin(), parent.end(), 0);
+    std::function<int(int)> find = [&](int a) { return parent[a] == a ? a : parent[a] = find(parent[a]); };
+    for (int st = 0; st < nst; ++st) {
+      if (!small[st]) continue;
+      for (int i : s.steps[st].in) {
+        const int pr = s.tensors[i].producer;
+        if (!s.tensors[i].leaf && pr >= 0 && small[pr]) parent[find(pr)] = find(st);
+      }
+    }
+    std::map<int, int> comp_of_rep;
+    std::vector<int> comp(nst, -1);
+    for (int st = 0; st < nst; ++st) {
+      if (!small[st]) continue;
+      int r = find(st);
+      auto it = comp_of_rep.find(r);
+      if (it == comp_of_rep.end()) {
+        it = comp_of_rep.emplace(r, (int)x.programs.size()).first;
+        x.programs.emplace_back();
+      }
+      comp[st] = it->second;
+      x.programs[it->second].steps.push_back(st);
+    }
+    for (auto &P : x.programs) {
+      // the root is the one step whose output leaves the component
+      int roots = 0;
+      for (int st : P.steps) {
+        const int o = s.steps[st].out;
+        const int c = consumer[o];
+        if (c < 0 || !small[c]) {
+          P.root = o;
+          ++roots;
+        }
+      }
+      if (roots != 1) throw std::runtime_error("small-step component is not a tree");
+      P.bdep = s.tensors[P.root].bdep;
+      P.sdep = s.tensors[P.root].sdep;
+      pack(P, false);
+    }
+    // launch sequence: every component without grid-step inputs first, then
+    // grid steps in order, each preceded by the components it consumes
+    std::vector<char> needs_grid(x.programs.size(), 0), launched(x.programs.size(), 0);
+    for (size_t c = 0; c < x.programs.size(); ++c)
+      for (int st : x.programs[c].steps)
+        for (int i : s.steps[st].in) {
+          const int pr = s.tensors[i].producer;
+          if (!s.tensors[i].leaf && pr >= 0 && !small[pr]) needs_grid[c] = 1;
+        }
+    LaunchGroup g0;
+    for (size_t c = 0; c < x.programs.size(); ++c)
+      if (!needs_grid[c]) {
+        g0.programs.push_back((int)c);
+        launched[c] = 1;
+      }
+    if (!g0.programs.empty()) x.launches.push_back(g0);
+    for (int st = 0; st < nst; ++st) {
+      if (small[st]) continue;
+      LaunchGroup pre;
+      for (int i : s.steps[st].in) {
+        const int pr = s.tensors[i].producer;
+        if (s.tensors[i].leaf || pr < 0 || !small[pr]) continue;
+        const int c = comp[pr];
+        if (!launched[c]) {
+          pre.programs.push_back(c);
+          launched[c] = 1;
+        }
+      }
+      if (!pre.programs.empty()) x.launches.push_back(pre);
+      LaunchGroup g;
+      g.kind = 1;
+      g.step = st;
+      x.launches.push_back(g);
+    }
+    LaunchGroup tail;
+    for (size_t c = 0; c < x.programs.size(); ++c)
+      if (!launched[c]) tail.programs.push_back((int)c);
+    if (!tail.programs.empty()) x.launches.push_back(tail);
+  }
+  for (auto &P : x.programs) {
+    x.lds_bytes = std::max(x.lds_bytes, P.lds_bytes);
+    x.scratch_per_wg = std::max(x.scratch_per_wg, P.scratch_bytes);
+  }
+  return x;
+}
+
+Layout layout(Schedule &s, const ExecPlan &x, uint64_t B, uint64_t S, uint64_t wg_slots) {
+  Layout L;
+  L.S = S;
+  FirstFit ff;
   auto bytes_of = [&](const Tensor &t) {
     return align256(instances(t, B, S) * ((uint64_t)1 << t.rank()) * (uint64_t)elem_bytes(t));
   };
-  uint64_t peak = 0;
-  for (size_t st = 0; st < s.steps.size(); ++st) {
-    Tensor &c = s.tensors[s.steps[st].out];
-    c.data_off = alloc(bytes_of(c));
-    peak = std::max(peak, top);
-    for (int i : s.steps[st].in) {
-      Tensor &t = s.tensors[i];
-      if (!t.leaf && t.last_use == (int)st) release(t.data_off, bytes_of(t));
-    }
+  auto global = [&](int t) { return !s.tensors[t].leaf && x.loc[t] == LOC_GLOBAL; };
+  // Liveness follows the launch sequence: the steps of one launch run
+  // concurrently, so everything a launch writes is placed before anything it
+  // reads last is released.
+  const size_t nl = x.launches.size();
+  std::vector<std::vector<int>> lsteps(nl);
+  for (size_t g = 0; g < nl; ++g) {
+    const LaunchGroup &G = x.launches[g];
+    if (G.kind == 1)
+      lsteps[g].push_back(G.step);
+    else
+      for (int p : G.programs)
+        for (int st : x.programs[p].steps) lsteps[g].push_back(st);
   }
-  L.data_bytes = align256(peak);
+  std::vector<int> last_launch(s.tensors.size(), -1);
+  for (size_t g = 0; g < nl; ++g)
+    for (int st : lsteps[g])
+      for (int i : s.steps[st].in) last_launch[i] = std::max(last_launch[i], (int)g);
+  last_launch[s.result] = (int)nl;  // read by the slice sum
+  for (size_t g = 0; g < nl; ++g) {
+    for (int st : lsteps[g]) {
+      const int o = s.steps[st].out;
+      if (!global(o)) continue;
+      uint64_t off;
+      ff.alloc(bytes_of(s.tensors[o]), off);
+      s.tensors[o].data_off = off;
+    }
+    std::vector<int> done;
+    for (int st : lsteps[g])
+      for (int i : s.steps[st].in)
+        if (global(i) && last_launch[i] == (int)g && std::find(done.begin(), done.end(), i) == done.end()) {
+          ff.release(s.tensors[i].data_off, bytes_of(s.tensors[i]));
+          done.push_back(i);
+        }
+  }
+  // self-check: tensors whose launch intervals overlap never share memory
+  {
+    std::vector<int> first_launch(s.tensors.size(), -1);
+    for (size_t g = 0; g < nl; ++g)
+      for (int st : lsteps[g]) first_launch[s.steps[st].out] = (int)g;
+    std::vector<int> gl;
+    for (size_t t = 0; t < s.tensors.size(); ++t)
+      if (global((int)t) && first_launch[t] >= 0) gl.push_back((int)t);
+    for (size_t a = 0; a < gl.size(); ++a)
+      for (size_t b = a + 1; b < gl.size(); ++b) {
+        const int u = gl[a], v = gl[b];
+        const bool live = first_launch[u] <= last_launch[v] && first_launch[v] <= last_launch[u];
+        const uint64_t u0 = s.tensors[u].data_off, u1 = u0 + bytes_of(s.tensors[u]);
+        const uint64_t v0 = s.tensors[v].data_off, v1 = v0 + bytes_of(s.tensors[v]);
+        if (live && u0 < v1 && v0 < u1) throw std::runtime_error("workspace layout overlap");
+      }
+  }
+  L.data_bytes = align256(ff.peak);
   uint64_t eo = L.data_bytes;
-  for (auto &t : s.tensors) {
-    if (t.leaf) continue;
-    t.exp_off = eo;
-    eo += align256(instances(t, B, S) * 8);
+  for (size_t t = 0; t < s.tensors.size(); ++t) {
+    if (!global((int)t)) continue;
+    s.tensors[t].exp_off = eo;
+    eo += align256(instances(s.tensors[t], B, S) * 4 * (1 + kMaxSlots));
   }
   L.exp_bytes = eo - L.data_bytes;
   L.partial_off = eo;
-  L.total_bytes = align256(eo + B * 32);
+  L.scratch_off = align256(eo + B * 32);
+  L.wg_slots = wg_slots;
+  L.total_bytes = align256(L.scratch_off + wg_slots * align256(x.scratch_per_wg));
   return L;
 }
 

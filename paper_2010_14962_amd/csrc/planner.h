@@ -15,6 +15,12 @@ using cd = std::complex<double>;
 constexpr int kMaxIn = 8;        // inputs of one fused contraction step
 constexpr int kLeafMaxRank = 12; // largest merged leaf group
 constexpr int kAlwaysF64Rank = 8; // intermediates below this rank stay complex128
+constexpr int kSmallRank = 11;    // steps with fewer output bits run inside one workgroup
+constexpr int kMaxStreamKappa = 4; // summed variables per streaming pass
+// Each rescaled workspace tensor keeps, per instance, its exponent and the
+// maximum magnitude of its entries spread over kMaxSlots words, so that the
+// many blocks writing one instance do not all update one address.
+constexpr int kMaxSlots = 32;
 
 // One gate factor of the merged binary network (Sec. II A, Fig. 1).
 struct Factor {
@@ -129,12 +135,53 @@ struct InputTables {
 uint32_t pext32(uint32_t x, uint32_t mask);
 InputTables input_tables(uint32_t mask, int rC, int nk);
 
+// ---------------------------------------------------------------------------
+// Execution plan: which steps run inside one workgroup and where every tensor
+// lives.
+// ---------------------------------------------------------------------------
+enum Loc : int { LOC_LDS = 0, LOC_SCRATCH = 1, LOC_GLOBAL = 2, LOC_LEAF = 3 };
+enum ExecMode : int { MODE_WIDE = 0, MODE_SLICE = 1 };
+
+// A tree of steps executed in order by one workgroup per instance.
+struct Program {
+  std::vector<int> steps;       // schedule step indices, ascending
+  int root = -1;                // output tensor of the last step
+  bool bdep = false, sdep = false;
+  uint32_t lds_bytes = 0;       // LDS tensors (complex128)
+  uint64_t scratch_bytes = 0;   // per-workgroup global scratch
+  int nslots = 0;               // program-local exponent slots
+};
+
+struct LaunchGroup {
+  int kind = 0;                 // 0 workgroup programs, 1 one grid-wide step
+  std::vector<int> programs;
+  int step = -1;
+};
+
+struct ExecPlan {
+  int mode = MODE_WIDE;
+  std::vector<Program> programs;
+  std::vector<LaunchGroup> launches;
+  std::vector<int> loc;         // per tensor
+  std::vector<uint64_t> off;    // LDS or scratch byte offset
+  std::vector<int> slot;        // exponent slot of LDS / scratch tensors
+  uint32_t lds_bytes = 0;       // largest program LDS footprint
+  uint64_t scratch_per_wg = 0;
+};
+
+// MODE_WIDE: trees of small steps become workgroup programs, the rest run as
+// grid-wide steps.  MODE_SLICE: the whole schedule is one program per
+// (bitstring, slice) instance.
+ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget);
+
 struct Layout {
   uint64_t S = 1;                // slices per wave
   uint64_t data_bytes = 0;       // intermediates region
   uint64_t exp_bytes = 0;        // exponents region
   uint64_t total_bytes = 0;
   uint64_t partial_off = 0;      // running per-bitstring partials
+  uint64_t scratch_off = 0;      // per-workgroup scratch region
+  uint64_t wg_slots = 0;
 };
 
 // Instance count of a tensor inside a wave.
@@ -151,7 +198,9 @@ int assign_storage(Schedule &s, int precision, double small_share = 0.03);
 
 inline int elem_bytes(const Tensor &t) { return t.f64 ? 16 : 8; }
 
-Layout layout(Schedule &s, uint64_t B, uint64_t S);
+// Workspace: GLOBAL tensors (first-fit with liveness), their exponents,
+// per-workgroup scratch for `wg_slots` workgroups, partial sums.
+Layout layout(Schedule &s, const ExecPlan &x, uint64_t B, uint64_t S, uint64_t wg_slots);
 
 struct Costs {
   double flops_per_slice = 0;    // all bitstrings

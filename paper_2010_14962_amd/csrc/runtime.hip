@@ -1,8 +1,14 @@
-// Device side of libqtn for gfx950: plan upload, the fused contraction step
-// kernel (Eq. (1) generalised to several operands and summed indices) and the
+// Device side of libqtn for gfx950: plan upload, the contraction kernels
+// (Eq. (1) generalised to several operands and summed indices) and the
 // compensated FP64 slice sum (Eq. (2); the master-side sum of Sec. III A).
+//
+// Two kinds of launches execute a wave of (bitstring, slice) instances:
+//   * workgroup programs: one workgroup runs a tree of steps for one instance,
+//     its intermediates in LDS (complex128) or per-workgroup scratch;
+//   * grid-wide steps: one large step over all instances and output elements.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -14,50 +20,61 @@
 namespace qtn {
 
 // ---------------------------------------------------------------------------
-// Descriptors passed by value to the step kernels.
+// Descriptors
 // ---------------------------------------------------------------------------
-struct InDesc {
-  const void *base;       // element 0 of the tensor (leaf block or workspace)
+struct OpDesc {
+  const void *base;       // GLOBAL: workspace tensor; LEAF: leaf block
   uint64_t bstride;       // elements between bitstrings
   uint64_t sstride;       // elements between slice-local instances
   uint64_t vsize;         // leaves: elements per slice variant
   const uint32_t *tab;    // lo[256] | mid[16] | kap[2^nk]
-  const int *E;           // scaled intermediates: accumulated exponent per instance
-  const uint32_t *M;      // scaled intermediates: max |component| (float bits)
+  int *E;                 // GLOBAL scaled tensors: exponent per instance
+  uint32_t *M;            // GLOBAL scaled tensors: max |component| exponent bits
   uint32_t ebstride, esstride;
   uint32_t selmask;       // leaves: slice bits that pick the variant
   uint32_t hi_mask, hi_shift;
+  uint32_t loc;           // Loc
   uint32_t f64;           // stored as complex128 (else complex64)
+  uint32_t off;           // LDS / scratch byte offset
+  int slot;               // LDS / scratch: exponent slot
+  uint32_t cvary;         // index depends on the output element
 };
 
-struct StepDesc {
-  InDesc in[kMaxIn];
-  void *out;
-  int *oE;
-  uint32_t *oM;
-  uint64_t obstride, osstride;
-  uint32_t oebstride, oesstride;
+struct PStep {
+  OpDesc in[kMaxIn];      // operands varying with the output element first
+  OpDesc out;
   int nin, rC, nk;
-  uint32_t nb, ns;        // instance grid of the launch
-  uint64_t s_lo;          // global slice index of slice-local 0
+  int nvary;              // in[0..nvary) vary with the output element
+  int nf32;               // of those, in[0..nf32) are stored as complex64
+};
+
+struct ProgDesc {
+  uint32_t step0, nsteps;
+  uint32_t bdep, sdep;
 };
 
 struct DeviceState {
   int device = -1;
-  void *leafbuf = nullptr;                        // complex128 gate factors
-  uint32_t *tabbuf = nullptr;
-  std::vector<uint64_t> leaf_elem_off;            // per tensor
-  std::vector<std::vector<uint64_t>> tab_off;     // per step, per input (uint32 units)
+  int mode = MODE_WIDE;
+  void *leafbuf = nullptr;        // complex128 gate factors
+  uint32_t *tabbuf = nullptr;     // index tables
+  PStep *stepbuf = nullptr;       // program steps, contiguous per program
+  ProgDesc *progbuf = nullptr;
+  int *plistbuf = nullptr;        // program ids of every launch group
+  std::vector<uint64_t> leaf_elem_off;
+  std::vector<std::vector<uint64_t>> tab_off;
+  std::vector<PStep> steps;       // one descriptor per schedule step (host copy)
+  std::vector<uint64_t> group_plist_off;
   char *ws = nullptr;
   uint64_t ws_bytes = 0;
   Layout L;
-  std::vector<StepDesc> descs;
+  uint32_t lds_bytes = 0, lds_total = 0;
+  int max_slots = 0;
   // optional per-launch timing of the streaming step kernel
   bool timing = false;
-  std::vector<hipEvent_t> ev;      // start/stop pairs
+  std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
-  std::vector<double> ev_bytes;    // algorithmic bytes of each timed launch
-  std::vector<double> ev_flops;
+  std::vector<double> ev_bytes, ev_flops;
   double t_ms = 0, t_bytes = 0, t_flops = 0;
   uint64_t t_launches = 0;
   std::vector<double> step_bytes, step_flops;  // per instance of each step
@@ -66,11 +83,15 @@ struct DeviceState {
 void device_state_free(DeviceState *d) {
   if (!d) return;
   for (auto e : d->ev) (void)hipEventDestroy(e);
-  if (d->leafbuf) (void)hipFree(d->leafbuf);
-  if (d->tabbuf) (void)hipFree(d->tabbuf);
+  for (void *p : {(void *)d->leafbuf, (void *)d->tabbuf, (void *)d->stepbuf,
+                  (void *)d->progbuf, (void *)d->plistbuf})
+    if (p) (void)hipFree(p);
   delete d;
 }
 
+// ---------------------------------------------------------------------------
+// Device helpers
+// ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t dpext(uint32_t x, uint32_t m) {
   uint32_t r = 0;
   uint32_t k = 0;
@@ -90,10 +111,17 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return r;
 }
 
-__device__ __forceinline__ double2 load_c(const InDesc &in, uint64_t i) {
-  if (in.f64) return ((const double2 *)in.base)[i];
-  const float2 f = ((const float2 *)in.base)[i];
+__device__ __forceinline__ double2 load_g(const void *base, uint32_t f64, uint64_t i) {
+  if (f64) return ((const double2 *)base)[i];
+  const float2 f = ((const float2 *)base)[i];
   return make_double2((double)f.x, (double)f.y);
+}
+
+__device__ __forceinline__ void store_g(void *base, uint32_t f64, uint64_t i, double2 v) {
+  if (f64)
+    ((double2 *)base)[i] = v;
+  else
+    ((float2 *)base)[i] = make_float2((float)v.x, (float)v.y);
 }
 
 // Exponent e with 2^(e-1) <= x < 2^e for the positive float with bits `b`
@@ -103,9 +131,233 @@ __device__ __forceinline__ int exp_of_bits(uint32_t b) {
   return be == 0 ? 0 : be - 126;
 }
 
-// Per-instance part of every operand offset, and the exponent bookkeeping of
-// the scaled form: inputs are read as mantissa * 2^E; the product is scaled by
-// 2^-(sum of input max-exponents) so the stored result stays near 1.
+// Exponent field of the larger component magnitude of the value as stored.
+__device__ __forceinline__ uint32_t max_bits(double2 v, uint32_t f64) {
+  const float ax = f64 ? (float)fabs(v.x) : fabsf((float)v.x);
+  const float ay = f64 ? (float)fabs(v.y) : fabsf((float)v.y);
+  return max(__float_as_uint(ax), __float_as_uint(ay)) & 0x7F800000u;
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t m) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, o, 64));
+  return m;
+}
+
+// Block-wide max over 256 threads; every thread must call it.
+__device__ __forceinline__ uint32_t block_max(uint32_t m, uint32_t *red4) {
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = m;
+  __syncthreads();
+  const uint32_t r = max(max(red4[0], red4[1]), max(red4[2], red4[3]));
+  __syncthreads();
+  return r;
+}
+
+// Raise the instance maximum (a no-return atomic; zero never raises it).
+__device__ __forceinline__ void raise_max(uint32_t *slot, uint32_t m) {
+  if (m) atomicMax(slot, m);
+}
+
+// Maximum over the kMaxSlots words of one instance (any thread, serial).
+__device__ __forceinline__ uint32_t slots_max(const uint32_t *M) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int k = 0; k < kMaxSlots; ++k) m = max(m, M[k]);
+  return m;
+}
+
+__device__ __forceinline__ uint64_t inst_off(const OpDesc &o, uint32_t b, uint32_t sl, uint32_t s) {
+  uint64_t r = (uint64_t)b * o.bstride + (uint64_t)sl * o.sstride;
+  if (o.selmask) r += (uint64_t)dpext(s, o.selmask) * o.vsize;
+  return r;
+}
+
+__device__ __forceinline__ uint64_t cpart(const OpDesc &o, uint32_t c) {
+  uint64_t r = o.tab[c & 255u] + o.tab[256 + ((c >> 8) & 15u)];
+  if (o.hi_mask) r += (uint64_t)dpext(c >> 12, o.hi_mask) << o.hi_shift;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup programs
+// ---------------------------------------------------------------------------
+struct WgCtx {
+  double2 *lds;           // program tensors (complex128)
+  double2 *red;           // 256 partial sums
+  int *sE;                // exponent slots
+  uint32_t *sM;
+  uint32_t *red4;
+  char *scratch;          // this workgroup's global scratch
+};
+
+template <bool SCALE>
+__device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, const WgCtx &W) {
+  const int nin = st.nin, rC = st.rC, nk = st.nk;
+  const uint32_t t = threadIdx.x;
+  const char *gptr[kMaxIn];
+  int sh = 0, esum = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxIn; ++i) {
+    gptr[i] = nullptr;
+    if (i >= nin) continue;
+    const OpDesc &o = st.in[i];
+    if (o.loc == LOC_SCRATCH) {
+      gptr[i] = W.scratch + o.off;
+    } else if (o.loc == LOC_GLOBAL || o.loc == LOC_LEAF) {
+      const uint64_t es = (o.loc == LOC_LEAF || o.f64) ? 16 : 8;
+      gptr[i] = (const char *)o.base + inst_off(o, b, sl, s) * es;
+    }
+    if (SCALE) {
+      if (o.loc == LOC_LDS || o.loc == LOC_SCRATCH) {
+        const int e = exp_of_bits(W.sM[o.slot]);
+        sh += e;
+        esum += W.sE[o.slot] + e;
+      } else if (o.loc == LOC_GLOBAL) {
+        const uint32_t qi = b * o.ebstride + sl * o.esstride;
+        const int e = exp_of_bits(slots_max(o.M + (uint64_t)qi * kMaxSlots));
+        sh += e;
+        esum += o.E[qi] + e;
+      }
+    }
+  }
+  auto point = [&](uint32_t c, uint32_t kap) -> double2 {
+    double2 prod = make_double2(1.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < kMaxIn; ++i) {
+      if (i >= nin) continue;
+      const OpDesc &o = st.in[i];
+      const uint32_t idx = (uint32_t)cpart(o, c) + o.tab[272 + kap];
+      double2 v;
+      if (o.loc == LOC_LDS)
+        v = W.lds[o.off / 16 + idx];
+      else
+        v = load_g(gptr[i], o.loc == LOC_LEAF ? 1u : o.f64, idx);
+      prod = (i == 0) ? v : cmul(prod, v);
+    }
+    return prod;
+  };
+  const OpDesc &out = st.out;
+  char *optr = nullptr;
+  if (out.loc == LOC_SCRATCH)
+    optr = W.scratch + out.off;
+  else if (out.loc == LOC_GLOBAL)
+    optr = (char *)out.base + ((uint64_t)b * out.bstride + (uint64_t)sl * out.sstride) * (out.f64 ? 16 : 8);
+  const uint32_t of64 = out.loc == LOC_LDS ? 1u : out.f64;
+  auto put = [&](uint32_t c, double2 v) {
+    if (out.loc == LOC_LDS)
+      W.lds[out.off / 16 + c] = v;
+    else
+      store_g(optr, out.f64, c, v);
+  };
+  const uint32_t nC = 1u << rC;
+  uint32_t mx = 0;
+  if (rC >= 8) {
+    const uint32_t nkap = 1u << nk;
+    for (uint32_t c = t; c < nC; c += 256) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (uint32_t k = 0; k < nkap; ++k) {
+        const double2 p = point(c, k);
+        acc.x += p.x;
+        acc.y += p.y;
+      }
+      if (SCALE) {
+        acc.x = ldexp(acc.x, -sh);
+        acc.y = ldexp(acc.y, -sh);
+        mx = max(mx, max_bits(acc, of64));
+      }
+      put(c, acc);
+    }
+  } else {
+    // Threads cover the low 8 bits of the index kappa:c; the kappa bits
+    // among them are summed by a fixed-order tree through LDS.
+    const int kb = min(nk, 8 - rC);
+    const uint32_t c = t & (nC - 1u);
+    const uint32_t kl = t >> rC;
+    double2 acc = make_double2(0.0, 0.0);
+    if (kl < (1u << kb)) {
+      const uint32_t nkh = 1u << (nk - kb);
+      for (uint32_t kh = 0; kh < nkh; ++kh) {
+        const double2 p = point(c, (kh << kb) | kl);
+        acc.x += p.x;
+        acc.y += p.y;
+      }
+    }
+    W.red[t] = acc;
+    __syncthreads();
+    for (uint32_t h = (1u << kb) >> 1; h >= 1; h >>= 1) {
+      if (kl < h) {
+        const double2 o = W.red[t + (h << rC)];
+        W.red[t].x += o.x;
+        W.red[t].y += o.y;
+      }
+      __syncthreads();
+    }
+    if (t < nC) {
+      acc = W.red[t];
+      if (SCALE) {
+        acc.x = ldexp(acc.x, -sh);
+        acc.y = ldexp(acc.y, -sh);
+        mx = max_bits(acc, of64);
+      }
+      put(c, acc);
+    }
+  }
+  if (SCALE) {
+    mx = block_max(mx, W.red4);
+    if (t == 0) {
+      if (out.loc == LOC_GLOBAL) {
+        const uint32_t qo = b * out.ebstride + sl * out.esstride;
+        out.E[qo] = esum;
+        out.M[(uint64_t)qo * kMaxSlots] = mx;
+      } else {
+        W.sE[out.slot] = esum;
+        W.sM[out.slot] = mx;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Persistent workgroups walk the items of one launch group.  The items of
+// program j are its instances, (bitstring, slice) or fewer when the program's
+// root does not depend on them; item -> (program, instance) by scanning the
+// group's program list.  Items never wait on each other.
+template <bool SCALE>
+__global__ __launch_bounds__(256) void wg_programs(const PStep *steps, const ProgDesc *progs,
+                                                   const int *plist, uint32_t nprog,
+                                                   uint32_t nbits, uint32_t total, uint64_t s_lo,
+                                                   uint32_t ns_wave, char *scratch,
+                                                   uint64_t scratch_per_wg, uint32_t lds_bytes,
+                                                   int max_slots) {
+  extern __shared__ __align__(16) char smem[];
+  WgCtx W;
+  W.lds = (double2 *)smem;
+  W.red = (double2 *)(smem + lds_bytes);
+  W.sE = (int *)(smem + lds_bytes + 256 * 16);
+  W.sM = (uint32_t *)(W.sE + max_slots);
+  W.red4 = W.sM + max_slots;
+  W.scratch = scratch + (uint64_t)blockIdx.x * scratch_per_wg;
+  for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
+    uint32_t q = item, j = 0;
+    ProgDesc P = progs[plist[0]];
+    for (;;) {
+      const uint32_t n = (P.bdep ? nbits : 1u) * (P.sdep ? ns_wave : 1u);
+      if (q < n || j + 1 >= nprog) break;
+      q -= n;
+      P = progs[plist[++j]];
+    }
+    const uint32_t ns = P.sdep ? ns_wave : 1u;
+    const uint32_t b = q / ns;
+    const uint32_t sl = q - b * ns;
+    const uint32_t s = (uint32_t)(s_lo + sl);
+    for (uint32_t k = 0; k < P.nsteps; ++k) wg_step<SCALE>(steps[P.step0 + k], b, sl, s, W);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Grid-wide steps (operands in the workspace or leaves)
+// ---------------------------------------------------------------------------
 struct InstanceSetup {
   uint64_t off[kMaxIn];
   int sh, esum;
@@ -114,108 +366,158 @@ struct InstanceSetup {
 };
 
 template <bool SCALE>
-__device__ __forceinline__ void setup_instance(const StepDesc &d, uint64_t q, InstanceSetup &I) {
-  const uint32_t b = (uint32_t)(q / d.ns);
-  const uint32_t sl = (uint32_t)(q - (uint64_t)b * d.ns);
-  const uint32_t s = (uint32_t)(d.s_lo + sl);
+__device__ __forceinline__ void setup_instance(const PStep &d, uint32_t ns, uint64_t q,
+                                               uint64_t s_lo, InstanceSetup &I) {
+  const uint32_t b = (uint32_t)(q / ns);
+  const uint32_t sl = (uint32_t)(q - (uint64_t)b * ns);
+  const uint32_t s = (uint32_t)(s_lo + sl);
   I.sh = 0;
   I.esum = 0;
 #pragma unroll
   for (int i = 0; i < kMaxIn; ++i) {
     if (i < d.nin) {
-      const InDesc &in = d.in[i];
-      uint64_t o = (uint64_t)b * in.bstride + (uint64_t)sl * in.sstride;
-      if (in.selmask) o += (uint64_t)dpext(s, in.selmask) * in.vsize;
-      I.off[i] = o;
-      if (SCALE && in.E) {
+      const OpDesc &in = d.in[i];
+      I.off[i] = inst_off(in, b, sl, s);
+      if (SCALE && in.loc == LOC_GLOBAL) {
         const uint32_t qi = b * in.ebstride + sl * in.esstride;
-        const int e = exp_of_bits(in.M[qi]);
+        const int e = exp_of_bits(slots_max(in.M + (uint64_t)qi * kMaxSlots));
         I.sh += e;
         I.esum += in.E[qi] + e;
       }
     }
   }
-  I.qo = b * d.oebstride + sl * d.oesstride;
-  I.obase = (uint64_t)b * d.obstride + (uint64_t)sl * d.osstride;
+  I.qo = b * d.out.ebstride + sl * d.out.esstride;
+  I.obase = (uint64_t)b * d.out.bstride + (uint64_t)sl * d.out.sstride;
 }
 
-// Sum over kappa of the operand product at output element c (FP64 registers).
-__device__ __forceinline__ double2 contract_point(const StepDesc &d, const uint64_t *cidx,
-                                                  uint32_t nkap) {
+__device__ __forceinline__ double2 grid_point(const PStep &d, const uint64_t *cidx, uint32_t nkap) {
   double2 acc = make_double2(0.0, 0.0);
   for (uint32_t kk = 0; kk < nkap; ++kk) {
-    double2 prod = load_c(d.in[0], cidx[0] + d.in[0].tab[272 + kk]);
+    double2 prod = load_g(d.in[0].base, d.in[0].f64, cidx[0] + d.in[0].tab[272 + kk]);
 #pragma unroll
     for (int i = 1; i < kMaxIn; ++i)
-      if (i < d.nin) prod = cmul(prod, load_c(d.in[i], cidx[i] + d.in[i].tab[272 + kk]));
+      if (i < d.nin) prod = cmul(prod, load_g(d.in[i].base, d.in[i].f64, cidx[i] + d.in[i].tab[272 + kk]));
     acc.x += prod.x;
     acc.y += prod.y;
   }
   return acc;
 }
 
-template <bool OUT64>
-__device__ __forceinline__ void store_c(void *base, uint64_t i, double2 v) {
-  if (OUT64)
-    ((double2 *)base)[i] = v;
-  else
-    ((float2 *)base)[i] = make_float2((float)v.x, (float)v.y);
-}
-
-template <bool OUT64>
-__device__ __forceinline__ uint32_t max_bits(double2 v) {
-  // magnitude of the stored value, as non-negative float bits (order-preserving)
-  const float ax = OUT64 ? (float)fabs(v.x) : fabsf((float)v.x);
-  const float ay = OUT64 ? (float)fabs(v.y) : fabsf((float)v.y);
-  return max(__float_as_uint(ax), __float_as_uint(ay));
-}
-
-// Streaming steps (output of >= 2^12 elements per instance): blockIdx.y walks
-// the (bitstring, slice) instances, x-blocks stream the output elements.  All
-// per-instance offsets and exponents are block-uniform.
-template <bool SCALE, bool OUT64>
-__global__ __launch_bounds__(256) void step_stream(const StepDesc d) {
-  const uint64_t Q = (uint64_t)d.nb * d.ns;
+// Streaming steps (output of >= 2^kStreamMinRank elements per instance).
+// blockIdx.y walks the instances; each x-block owns chunks of 4096
+// consecutive output elements.  Thread t always handles elements with low
+// bits t, so its per-lane index part is fixed; the mid/high parts and the
+// kappa offsets are block-uniform and come from LDS.  Operands that do not
+// depend on the output element (gate factors on summed variables) are folded
+// into one coefficient per kappa value, computed once per instance.
+template <bool SCALE, int NK, int NV, int NF>
+__global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, uint32_t ns,
+                                                   uint64_t s_lo, uint32_t jspan) {
+  constexpr uint32_t NKAP = 1u << NK;
+  __shared__ uint32_t s_mid[NV][16];
+  __shared__ uint32_t s_kap[NV][NKAP];
+  __shared__ double2 s_coef[NKAP];
+  __shared__ uint32_t red4[4];
+  const uint32_t t = threadIdx.x;
+  if (t < NV * 16) s_mid[t >> 4][t & 15] = d.in[t >> 4].tab[256 + (t & 15)];
+  if (t < NV * NKAP) s_kap[t / NKAP][t % NKAP] = d.in[t / NKAP].tab[272 + t % NKAP];
+  uint32_t lo[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) lo[v] = d.in[v].tab[t];
+  const uint64_t Q = (uint64_t)nb * ns;
   const uint32_t nC = 1u << d.rC;
-  const uint32_t nkap = 1u << d.nk;
+  // work units of the instance: jspan x 256 consecutive elements
+  const uint32_t units = (nC >> 8) / jspan;
   for (uint64_t q = blockIdx.y; q < Q; q += gridDim.y) {
     InstanceSetup I;
-    setup_instance<SCALE>(d, q, I);
-    uint32_t wmax = 0;
-    for (uint32_t c = blockIdx.x * 256u + threadIdx.x; c < nC; c += gridDim.x * 256u) {
-      uint64_t cidx[kMaxIn];
+    setup_instance<SCALE>(d, ns, q, s_lo, I);
+    __syncthreads();
+    if (t < NKAP) {
+      double2 c = make_double2(1.0, 0.0);
 #pragma unroll
-      for (int i = 0; i < kMaxIn; ++i) {
-        if (i < d.nin) {
-          const InDesc &in = d.in[i];
-          uint64_t o = I.off[i] + in.tab[c & 255u] + in.tab[256 + ((c >> 8) & 15u)];
-          if (in.hi_mask) o += (uint64_t)dpext(c >> 12, in.hi_mask) << in.hi_shift;
-          cidx[i] = o;
+      for (int i = NV; i < kMaxIn; ++i)
+        if (i < d.nin) c = cmul(c, load_g(d.in[i].base, d.in[i].f64, I.off[i] + d.in[i].tab[272 + t]));
+      s_coef[t] = c;
+    }
+    __syncthreads();
+    // per-lane operand pointers for this instance; in[0..NF) are complex64
+    const char *vp[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      vp[v] = (const char *)d.in[v].base + (I.off[v] + lo[v]) * (v < NF ? 8u : 16u);
+    char *op = (char *)d.out.base + I.obase * (d.out.f64 ? 16u : 8u);
+    const uint32_t of = d.out.f64;
+    const int sh = I.sh;
+    uint32_t wmax = 0;
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+      const uint32_t j0 = u * jspan;            // in units of 256 elements
+      const uint32_t ch = j0 >> 4;
+      uint32_t hoff[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) hoff[v] = dpext(ch, d.in[v].hi_mask) << d.in[v].hi_shift;
+#pragma unroll 1
+      for (uint32_t jj = 0; jj < jspan; ++jj) {
+        const uint32_t j = (j0 + jj) & 15u;
+        const uint32_t c = ((j0 + jj) << 8) | t;
+        double2 acc = make_double2(0.0, 0.0);
+        // all loads of a group of kappa values are issued before any product
+        constexpr uint32_t KU = NKAP > 4 ? 4 : NKAP;
+#pragma unroll 1
+        for (uint32_t kb = 0; kb < NKAP; kb += KU) {
+          float2 xf[KU][NF > 0 ? NF : 1];
+          double2 xd[KU][NV - NF > 0 ? NV - NF : 1];
+#pragma unroll
+          for (uint32_t kk = 0; kk < KU; ++kk) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const uint32_t idx = hoff[v] + s_mid[v][j] + s_kap[v][kb + kk];
+              if (v < NF)
+                xf[kk][v < NF ? v : 0] = ((const float2 *)vp[v])[idx];
+              else
+                xd[kk][v >= NF ? v - NF : 0] = ((const double2 *)vp[v])[idx];
+            }
+          }
+          // keep the loads above together so they are in flight at once
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (uint32_t kk = 0; kk < KU; ++kk) {
+            double2 prod = s_coef[kb + kk];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              const double2 x = v < NF ? make_double2((double)xf[kk][v < NF ? v : 0].x,
+                                                      (double)xf[kk][v < NF ? v : 0].y)
+                                       : xd[kk][v >= NF ? v - NF : 0];
+              prod = cmul(prod, x);
+            }
+            acc.x += prod.x;
+            acc.y += prod.y;
+          }
         }
+        if (SCALE) {
+          acc.x = ldexp(acc.x, -sh);
+          acc.y = ldexp(acc.y, -sh);
+          wmax = max(wmax, max_bits(acc, of));
+        }
+        store_g(op, of, c, acc);
       }
-      double2 acc = contract_point(d, cidx, nkap);
-      if (SCALE) {
-        acc.x = ldexp(acc.x, -I.sh);
-        acc.y = ldexp(acc.y, -I.sh);
-        wmax = max(wmax, max_bits<OUT64>(acc));
-      }
-      store_c<OUT64>(d.out, I.obase + c, acc);
     }
     if (SCALE) {
-      // nC is a multiple of 256: every lane of the block ran the same trips
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (uint32_t)__shfl_xor((int)wmax, o, 64));
-      if ((threadIdx.x & 63) == 0 && wmax) atomicMax(d.oM + I.qo, wmax);
-      if (blockIdx.x == 0 && threadIdx.x == 0) d.oE[I.qo] = I.esum;
+      // every thread of the block ran the same trips
+      const uint32_t m = block_max(wmax, red4);
+      if (t == 0) {
+        raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots + (blockIdx.x % kMaxSlots), m);
+        if (blockIdx.x == 0) d.out.E[I.qo] = I.esum;
+      }
     }
   }
 }
 
-// Small steps: one flat index over (instance, output element).
-template <bool SCALE, bool OUT64>
-__global__ __launch_bounds__(256) void step_small(const StepDesc d) {
+// Other grid-wide steps: one flat index over (instance, output element).
+template <bool SCALE>
+__global__ __launch_bounds__(256) void step_small(const PStep d, uint32_t nb, uint32_t ns,
+                                                  uint64_t s_lo) {
   const int rC = d.rC;
-  const uint64_t total = ((uint64_t)d.nb * d.ns) << rC;
+  const uint64_t total = ((uint64_t)nb * ns) << rC;
   const uint32_t cmask = (1u << rC) - 1u;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint32_t nkap = 1u << d.nk;
@@ -223,26 +525,27 @@ __global__ __launch_bounds__(256) void step_small(const StepDesc d) {
     const uint64_t q = G >> rC;
     const uint32_t c = (uint32_t)G & cmask;
     InstanceSetup I;
-    setup_instance<SCALE>(d, q, I);
+    setup_instance<SCALE>(d, ns, q, s_lo, I);
     uint64_t cidx[kMaxIn];
 #pragma unroll
-    for (int i = 0; i < kMaxIn; ++i) {
-      if (i < d.nin) {
-        const InDesc &in = d.in[i];
-        uint64_t o = I.off[i] + in.tab[c & 255u] + in.tab[256 + ((c >> 8) & 15u)];
-        if (in.hi_mask) o += (uint64_t)dpext(c >> 12, in.hi_mask) << in.hi_shift;
-        cidx[i] = o;
-      }
-    }
-    double2 acc = contract_point(d, cidx, nkap);
+    for (int i = 0; i < kMaxIn; ++i)
+      if (i < d.nin) cidx[i] = I.off[i] + cpart(d.in[i], c);
+    double2 acc = grid_point(d, cidx, nkap);
     if (SCALE) {
       acc.x = ldexp(acc.x, -I.sh);
       acc.y = ldexp(acc.y, -I.sh);
-      const uint32_t mb = max_bits<OUT64>(acc);
-      if (mb) atomicMax(d.oM + I.qo, mb);
-      if (c == 0) d.oE[I.qo] = I.esum;
+      uint32_t mb = max_bits(acc, d.out.f64);
+      if (rC >= 6) {
+        // the 64 lanes of a wave hold one instance (total is a multiple of 64)
+        mb = wave_max(mb);
+        if ((threadIdx.x & 63) == 0)
+          raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots + ((G >> 6) % kMaxSlots), mb);
+      } else {
+        raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots, mb);
+      }
+      if (c == 0) d.out.E[I.qo] = I.esum;
     }
-    store_c<OUT64>(d.out, I.obase + c, acc);
+    store_g((void *)d.out.base, d.out.f64, I.obase + c, acc);
   }
 }
 constexpr int kStreamMinRank = 12;
@@ -256,10 +559,10 @@ __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e
   e = (a - (s - bb)) + (b - bb);
 }
 
-template <bool RES64, bool SCALE>
-__global__ __launch_bounds__(256) void slice_sum(const void *res, const int *E, uint64_t bstride,
-                                                 uint64_t sstride, uint32_t ebstride,
-                                                 uint32_t esstride, uint32_t count, double pref,
+template <bool SCALE>
+__global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64, const int *E,
+                                                 uint64_t bstride, uint64_t sstride,
+                                                 uint32_t count, double pref,
                                                  qtn_partial *partials, int init) {
   __shared__ double sre[256], cre[256], sim[256], cim[256];
   const uint32_t b = blockIdx.x;
@@ -267,18 +570,10 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, const int *E, 
   double ar = 0, cr = 0, ai = 0, ci = 0;
   for (uint32_t sl = t; sl < count; sl += 256) {
     const uint64_t at = (uint64_t)b * bstride + (uint64_t)sl * sstride;
-    double vr, vi;
-    if (RES64) {
-      const double2 v = ((const double2 *)res)[at];
-      vr = v.x;
-      vi = v.y;
-    } else {
-      const float2 v = ((const float2 *)res)[at];
-      vr = (double)v.x;
-      vi = (double)v.y;
-    }
+    const double2 v = load_g(res, res64, at);
+    double vr = v.x, vi = v.y;
     if (SCALE) {
-      int e = E[b * ebstride + sl * esstride];
+      const int e = E[at];
       vr = ldexp(vr, e);
       vi = ldexp(vi, e);
     }
@@ -351,6 +646,15 @@ static int hip_fail(hipError_t e, const char *what) {
     if (_e != hipSuccess) return hip_fail(_e, #call); \
   } while (0)
 
+template <typename T>
+static int upload(T **dst, const std::vector<T> &src, const char *what) {
+  if (*dst) (void)hipFree(*dst);
+  *dst = nullptr;
+  hipError_t e = hipMalloc((void **)dst, std::max<size_t>(src.size(), 1) * sizeof(T));
+  if (e != hipSuccess) return hip_fail(e, what);
+  if (!src.empty()) HIP_TRY(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  return QTN_OK;
+}
 
 }  // namespace qtn
 
@@ -374,13 +678,30 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   const uint64_t maxS = P->cut.empty() ? 1 : (1ull << P->cut.size());
   if (S > maxS) S = maxS;
   Schedule &sch = P->sched;
-  Layout L = layout(sch, P->net.B, S);
+  const int mode = choose_mode(P, S);
+  const ExecPlan &X = P->exec[mode];
+  Layout L;
+  try {
+    L = layout(sch, X, P->net.B, S, wg_slots_for(P, mode, S));
+  } catch (const std::exception &e) {
+    set_error(e.what());
+    return QTN_ESTATE;
+  }
   if (bytes < L.total_bytes) {
     set_error("workspace too small: need " + std::to_string(L.total_bytes) + " bytes");
     return QTN_ENOMEM;
   }
   if (!P->cut.empty() && !sch.tensors[sch.result].sdep) {
     set_error("internal: sliced result does not depend on the slice");
+    return QTN_ESTATE;
+  }
+  // LDS of the program kernel: tensors | 256 partial sums | exponent slots | 4 words
+  int max_slots = 1;
+  for (const Program &pr : X.programs) max_slots = std::max(max_slots, pr.nslots);
+  const uint32_t lds_bytes = (X.lds_bytes + 15) & ~15u;
+  const uint32_t lds_total = lds_bytes + 256 * 16 + (uint32_t)(2 * max_slots + 4) * 4;
+  if (lds_total > 160 * 1024) {
+    set_error("program LDS footprint too large");
     return QTN_ESTATE;
   }
   int dev = 0;
@@ -404,15 +725,14 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
       const Tensor &T = sch.tensors[t];
       if (!T.leaf) continue;
       for (size_t i = 0; i < T.values.size(); ++i) {
-        uint64_t k = D->leaf_elem_off[t] + i;
+        const uint64_t k = D->leaf_elem_off[t] + i;
         host[2 * k] = T.values[i].real();
         host[2 * k + 1] = T.values[i].imag();
       }
     }
-    hipError_t e = hipMalloc(&D->leafbuf, host.size() * sizeof(double));
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(leaves)");
-    HIP_TRY(hipMemcpy(D->leafbuf, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice));
-    // index tables
+    double *lb = nullptr;
+    if (int rc = upload(&lb, host, "hipMalloc(leaves)")) return rc;
+    D->leafbuf = lb;
     std::vector<uint32_t> tabs;
     D->tab_off.assign(sch.steps.size(), {});
     for (size_t st = 0; st < sch.steps.size(); ++st) {
@@ -426,151 +746,240 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
         while (tabs.size() & 63) tabs.push_back(0);
       }
     }
-    e = hipMalloc((void **)&D->tabbuf, std::max<size_t>(tabs.size(), 1) * 4);
-    if (e != hipSuccess) return hip_fail(e, "hipMalloc(tables)");
-    HIP_TRY(hipMemcpy(D->tabbuf, tabs.data(), tabs.size() * 4, hipMemcpyHostToDevice));
+    if (int rc = upload(&D->tabbuf, tabs, "hipMalloc(tables)")) return rc;
   }
+  if (lds_total > 64 * 1024) {
+    HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
+    HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
+  }
+  D->mode = mode;
+  D->ws = (char *)dev_ptr;
+  D->ws_bytes = bytes;
+  D->L = L;
+  D->max_slots = max_slots;
+  D->lds_bytes = lds_bytes;
+  D->lds_total = lds_total;
+  const uint64_t B = P->net.B;
+  const bool scaled = P->precision != QTN_FP64;
   // algorithmic bytes and flops of each step, per instance
   D->step_bytes.assign(sch.steps.size(), 0.0);
   D->step_flops.assign(sch.steps.size(), 0.0);
   for (size_t st = 0; st < sch.steps.size(); ++st) {
     const Step &S_ = sch.steps[st];
-    const Tensor &O = sch.tensors[S_.out];
-    double by = std::ldexp((double)elem_bytes(O), S_.rC);
+    double by = std::ldexp((double)elem_bytes(sch.tensors[S_.out]), S_.rC);
     for (int i : S_.in) by += std::ldexp((double)elem_bytes(sch.tensors[i]), sch.tensors[i].rank());
     D->step_bytes[st] = by;
     D->step_flops[st] = std::ldexp(1.0, S_.nk + S_.rC) *
                         (6.0 * (double)(S_.in.size() - 1) + (S_.nk > 0 ? 2.0 : 0.0));
   }
-  D->ws = (char *)dev_ptr;
-  D->ws_bytes = bytes;
-  D->L = L;
-  // descriptors with workspace addresses
-  const uint64_t B = P->net.B;
-  const bool scaled = P->precision != QTN_FP64;
-  D->descs.assign(sch.steps.size(), StepDesc{});
+  // operand descriptors
+  auto describe = [&](int tid, OpDesc &o) {
+    const Tensor &T = sch.tensors[tid];
+    std::memset(&o, 0, sizeof(o));
+    o.loc = (uint32_t)X.loc[tid];
+    o.f64 = T.f64 ? 1u : 0u;
+    o.off = (uint32_t)X.off[tid];
+    o.slot = X.slot[tid];
+    const uint64_t size = 1ull << T.rank();
+    if (T.leaf) {
+      o.loc = LOC_LEAF;
+      o.f64 = 1;
+      o.base = (const double *)D->leafbuf + 2 * D->leaf_elem_off[tid];
+      o.vsize = size;
+      o.selmask = T.selmask;
+      o.bstride = T.bdep ? (size << __builtin_popcount(T.selmask)) : 0;
+    } else if (o.loc == LOC_GLOBAL) {
+      o.base = D->ws + T.data_off;
+      o.bstride = T.bdep ? (T.sdep ? S : 1) * size : 0;
+      o.sstride = T.sdep ? size : 0;
+      if (scaled) {
+        o.E = (int *)(D->ws + T.exp_off);
+        o.M = (uint32_t *)(D->ws + T.exp_off) + instances(T, B, S);  // kMaxSlots words each
+      }
+      o.ebstride = T.bdep ? (uint32_t)(T.sdep ? S : 1) : 0;
+      o.esstride = T.sdep ? 1 : 0;
+    }
+  };
+  D->steps.assign(sch.steps.size(), PStep{});
   for (size_t st = 0; st < sch.steps.size(); ++st) {
     const Step &S_ = sch.steps[st];
-    StepDesc &d = D->descs[st];
+    PStep &d = D->steps[st];
     std::memset(&d, 0, sizeof(d));
     d.nin = (int)S_.in.size();
     d.rC = S_.rC;
     d.nk = S_.nk;
-    for (size_t i = 0; i < S_.in.size(); ++i) {
-      const Tensor &T = sch.tensors[S_.in[i]];
-      InDesc &in = d.in[i];
+    // operands whose index depends on the output element come first
+    const uint32_t cbits = (S_.rC >= 32) ? 0xffffffffu : ((1u << S_.rC) - 1u);
+    // order: varying complex64, varying complex128, then the rest
+    std::vector<size_t> ord;
+    auto vary = [&](size_t i) { return (S_.mask[i] & cbits) != 0; };
+    auto is32 = [&](size_t i) { return !sch.tensors[S_.in[i]].leaf && !sch.tensors[S_.in[i]].f64; };
+    for (size_t i = 0; i < S_.in.size(); ++i)
+      if (vary(i) && is32(i)) ord.push_back(i);
+    d.nf32 = (int)ord.size();
+    for (size_t i = 0; i < S_.in.size(); ++i)
+      if (vary(i) && !is32(i)) ord.push_back(i);
+    for (size_t i = 0; i < S_.in.size(); ++i)
+      if (!vary(i)) ord.push_back(i);
+    d.nvary = 0;
+    for (size_t j = 0; j < ord.size(); ++j) {
+      const size_t i = ord[j];
+      describe(S_.in[i], d.in[j]);
       InputTables it = input_tables(S_.mask[i], S_.rC, S_.nk);
-      in.tab = D->tabbuf + D->tab_off[st][i];
-      in.hi_mask = it.hi_mask;
-      in.hi_shift = it.hi_shift;
-      in.f64 = T.f64 ? 1u : 0u;
-      const uint64_t size = 1ull << T.rank();
-      if (T.leaf) {
-        in.base = (const double *)D->leafbuf + 2 * D->leaf_elem_off[S_.in[i]];
-        in.vsize = size;
-        in.selmask = T.selmask;
-        in.bstride = T.bdep ? (size << __builtin_popcount(T.selmask)) : 0;
-        in.sstride = 0;
-      } else {
-        in.base = D->ws + T.data_off;
-        in.bstride = T.bdep ? (T.sdep ? S : 1) * size : 0;
-        in.sstride = T.sdep ? size : 0;
-        if (scaled) {
-          in.E = (const int *)(D->ws + T.exp_off);
-          in.M = (const uint32_t *)(D->ws + T.exp_off) + instances(T, B, S);
-        }
-        in.ebstride = T.bdep ? (uint32_t)(T.sdep ? S : 1) : 0;
-        in.esstride = T.sdep ? 1 : 0;
-      }
+      d.in[j].tab = D->tabbuf + D->tab_off[st][i];
+      d.in[j].hi_mask = it.hi_mask;
+      d.in[j].hi_shift = it.hi_shift;
+      d.in[j].cvary = (S_.mask[i] & cbits) ? 1u : 0u;
+      d.nvary += (int)d.in[j].cvary;
     }
-    const Tensor &O = sch.tensors[S_.out];
-    const uint64_t osize = 1ull << O.rank();
-    d.out = D->ws + O.data_off;
-    d.obstride = O.bdep ? (O.sdep ? S : 1) * osize : 0;
-    d.osstride = O.sdep ? osize : 0;
-    d.oE = (int *)(D->ws + O.exp_off);
-    d.oM = (uint32_t *)(D->ws + O.exp_off) + instances(O, B, S);
-    d.oebstride = O.bdep ? (uint32_t)(O.sdep ? S : 1) : 0;
-    d.oesstride = O.sdep ? 1 : 0;
-    d.nb = O.bdep ? (uint32_t)B : 1;
+    describe(S_.out, d.out);
   }
+  // program steps, contiguous per program
+  std::vector<PStep> packed;
+  std::vector<ProgDesc> progs;
+  for (const Program &pr : X.programs) {
+    ProgDesc pd;
+    pd.step0 = (uint32_t)packed.size();
+    pd.nsteps = (uint32_t)pr.steps.size();
+    pd.bdep = pr.bdep;
+    pd.sdep = pr.sdep;
+    for (int st : pr.steps) packed.push_back(D->steps[st]);
+    progs.push_back(pd);
+  }
+  if (int rc = upload(&D->stepbuf, packed, "hipMalloc(program steps)")) return rc;
+  if (int rc = upload(&D->progbuf, progs, "hipMalloc(programs)")) return rc;
+  std::vector<int> pl;
+  D->group_plist_off.clear();
+  for (const LaunchGroup &g : X.launches) {
+    D->group_plist_off.push_back(pl.size());
+    if (g.kind == 0) pl.insert(pl.end(), g.programs.begin(), g.programs.end());
+  }
+  if (int rc = upload(&D->plistbuf, pl, "hipMalloc(program lists)")) return rc;
   return QTN_OK;
 }
 
-template <bool SCALE, bool OUT64>
-static void launch_step(DeviceState *D, const StepDesc &d, hipStream_t stream) {
-  if (d.rC >= kStreamMinRank) {
-    const uint64_t Q = (uint64_t)d.nb * d.ns;
-    const uint32_t per_inst = (1u << d.rC) / 256u;
-    // about 8 waves of blocks over the chip, at least one block per instance
-    const uint64_t want = std::max<uint64_t>(1, 8192 / std::max<uint64_t>(Q, 1));
-    const unsigned gx = (unsigned)std::min<uint64_t>(per_inst, std::max<uint64_t>(want, 1));
-    const unsigned gy = (unsigned)std::min<uint64_t>(Q, 65535);
-    hipLaunchKernelGGL((step_stream<SCALE, OUT64>), dim3(gx, gy), dim3(256), 0, stream, d);
-  } else {
-    const uint64_t total = ((uint64_t)d.nb * d.ns) << d.rC;
-    const unsigned blocks =
-        (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
-    hipLaunchKernelGGL((step_small<SCALE, OUT64>), dim3(blocks), dim3(256), 0, stream, d);
+template <bool SCALE, int NK, int NV>
+static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint32_t nb, uint32_t ns,
+                             uint64_t s_lo, uint32_t jspan) {
+  // NF = number of complex64 operands among the NV varying ones
+  switch (d.nf32) {
+#define QTN_NF(F)                                                                                  \
+  case F:                                                                                          \
+    if constexpr (F <= NV)                                                                         \
+      hipLaunchKernelGGL((step_stream<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256), 0,      \
+                         stream, d, nb, ns, s_lo, jspan);                                          \
+    break;
+    QTN_NF(0) QTN_NF(1) QTN_NF(2) QTN_NF(3) QTN_NF(4)
+#undef QTN_NF
+    default: break;
   }
-  (void)D;
+}
+
+template <bool SCALE, int NK>
+static void launch_stream_nk(const PStep &d, dim3 grid, hipStream_t stream, uint32_t nb, uint32_t ns,
+                             uint64_t s_lo, uint32_t jspan) {
+  switch (d.nvary) {
+    case 1: launch_stream_nv<SCALE, NK, 1>(d, grid, stream, nb, ns, s_lo, jspan); break;
+    case 2: launch_stream_nv<SCALE, NK, 2>(d, grid, stream, nb, ns, s_lo, jspan); break;
+    case 3: launch_stream_nv<SCALE, NK, 3>(d, grid, stream, nb, ns, s_lo, jspan); break;
+    default: launch_stream_nv<SCALE, NK, 4>(d, grid, stream, nb, ns, s_lo, jspan); break;
+  }
+}
+
+template <bool SCALE>
+static void launch_stream(const PStep &d, dim3 grid, hipStream_t stream, uint32_t nb, uint32_t ns,
+                          uint64_t s_lo, uint32_t jspan) {
+  switch (d.nk) {
+    case 0: launch_stream_nk<SCALE, 0>(d, grid, stream, nb, ns, s_lo, jspan); break;
+    case 1: launch_stream_nk<SCALE, 1>(d, grid, stream, nb, ns, s_lo, jspan); break;
+    case 2: launch_stream_nk<SCALE, 2>(d, grid, stream, nb, ns, s_lo, jspan); break;
+    case 3: launch_stream_nk<SCALE, 3>(d, grid, stream, nb, ns, s_lo, jspan); break;
+    default: launch_stream_nk<SCALE, 4>(d, grid, stream, nb, ns, s_lo, jspan); break;
+  }
 }
 
 template <bool SCALE>
 static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream) {
   DeviceState *D = P->dev;
   const Schedule &sch = P->sched;
+  const ExecPlan &X = P->exec[D->mode];
   const uint64_t S = D->L.S;
   const uint64_t B = P->net.B;
   qtn_partial *partials = (qtn_partial *)(D->ws + D->L.partial_off);
   const Tensor &res = sch.tensors[sch.result];
+  const uint64_t scratch_stride = (X.scratch_per_wg + 255) & ~uint64_t(255);
   bool first = true;
   for (uint64_t s_lo = lo; s_lo < hi; s_lo += S) {
     const uint64_t cnt = std::min<uint64_t>(S, hi - s_lo);
-    if (SCALE) {
+    if (SCALE && D->L.exp_bytes) {
       const uint64_t words = D->L.exp_bytes / 4;
       hipLaunchKernelGGL(zero_words, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 4096)),
                          dim3(256), 0, stream, (uint32_t *)(D->ws + D->L.data_bytes), words);
     }
-    for (size_t st = 0; st < sch.steps.size(); ++st) {
-      StepDesc d = D->descs[st];
-      d.s_lo = s_lo;
-      d.ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
-      const bool out64 = sch.tensors[sch.steps[st].out].f64;
-      const bool timed = D->timing && d.rC >= kStreamMinRank;
-      if (timed) {
-        if (D->ev_used + 2 > D->ev.size()) {
-          for (int j = 0; j < 64; ++j) {
-            hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
-            D->ev.push_back(e);
-          }
+    for (size_t g = 0; g < X.launches.size(); ++g) {
+      const LaunchGroup &G = X.launches[g];
+      if (G.kind == 0) {
+        uint64_t total = 0;
+        for (int p : G.programs) {
+          const Program &pr = X.programs[p];
+          total += (pr.bdep ? B : 1) * (pr.sdep ? cnt : 1);
         }
-        HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
-      }
-      if (out64)
-        launch_step<SCALE, true>(D, d, stream);
-      else
-        launch_step<SCALE, false>(D, d, stream);
-      if (timed) {
-        HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
-        D->ev_used += 2;
-        const double q = (double)d.nb * d.ns;
-        D->ev_bytes.push_back(q * D->step_bytes[st]);
-        D->ev_flops.push_back(q * D->step_flops[st]);
+        const uint64_t cap = D->mode == MODE_SLICE ? D->L.wg_slots : 2048;
+        const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
+        hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), D->lds_total,
+                           stream, (const PStep *)D->stepbuf, (const ProgDesc *)D->progbuf,
+                           (const int *)(D->plistbuf + D->group_plist_off[g]),
+                           (uint32_t)G.programs.size(), (uint32_t)B, (uint32_t)total, s_lo,
+                           (uint32_t)cnt, D->ws + D->L.scratch_off, scratch_stride,
+                           D->lds_bytes, D->max_slots);
+      } else {
+        const int st = G.step;
+        const PStep &d = D->steps[st];
+        const uint32_t nb = sch.steps[st].bdep ? (uint32_t)B : 1;
+        const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
+        const uint64_t Q = (uint64_t)nb * ns;
+        const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
+        const bool timed = D->timing && streaming;
+        if (timed) {
+          if (D->ev_used + 2 > D->ev.size()) {
+            for (int j = 0; j < 64; ++j) {
+              hipEvent_t e;
+              HIP_TRY(hipEventCreate(&e));
+              D->ev.push_back(e);
+            }
+          }
+          HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
+        }
+        if (streaming) {
+          // units of jspan x 256 elements: about 2048 blocks over the chip
+          const uint32_t rows = (1u << d.rC) >> 8;
+          uint32_t jspan = 16;
+          while (jspan > 1 && (uint64_t)(rows / jspan) * Q < 2048) jspan >>= 1;
+          const uint64_t units = rows / jspan;
+          const uint64_t want = std::max<uint64_t>(1, 4096 / std::max<uint64_t>(Q, 1));
+          const dim3 grid((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
+          launch_stream<SCALE>(d, grid, stream, nb, ns, s_lo, jspan);
+        } else {
+          const uint64_t total = Q << d.rC;
+          const unsigned blocks =
+              (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
+          hipLaunchKernelGGL((step_small<SCALE>), dim3(blocks), dim3(256), 0, stream, d, nb, ns, s_lo);
+        }
+        if (timed) {
+          HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
+          D->ev_used += 2;
+          D->ev_bytes.push_back((double)Q * D->step_bytes[st]);
+          D->ev_flops.push_back((double)Q * D->step_flops[st]);
+        }
       }
     }
     const uint64_t rb = res.bdep ? (res.sdep ? S : 1) : 0, rs = res.sdep ? 1 : 0;
-    const void *rp = (const void *)(D->ws + res.data_off);
-    const int *re = (const int *)(D->ws + res.exp_off);
-    if (res.f64)
-      hipLaunchKernelGGL((slice_sum<true, SCALE>), dim3((unsigned)B), dim3(256), 0, stream, rp, re,
-                         rb, rs, (uint32_t)rb, (uint32_t)rs, (uint32_t)cnt, P->net.prefactor,
-                         partials, first ? 1 : 0);
-    else
-      hipLaunchKernelGGL((slice_sum<false, SCALE>), dim3((unsigned)B), dim3(256), 0, stream, rp, re,
-                         rb, rs, (uint32_t)rb, (uint32_t)rs, (uint32_t)cnt, P->net.prefactor,
-                         partials, first ? 1 : 0);
+    hipLaunchKernelGGL((slice_sum<SCALE>), dim3((unsigned)B), dim3(256), 0, stream,
+                       (const void *)(D->ws + res.data_off), res.f64 ? 1u : 0u,
+                       (const int *)(D->ws + res.exp_off), rb, rs, (uint32_t)cnt,
+                       P->net.prefactor, partials, first ? 1 : 0);
     first = false;
   }
   HIP_TRY(hipGetLastError());

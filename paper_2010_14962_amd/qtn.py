@@ -32,7 +32,7 @@ class QtnPlanOpts(ctypes.Structure):
     _fields_ = [("k", c_int32), ("max_rank", c_int32), ("k_max", c_int32),
                 ("cut_vars", POINTER(c_uint32)), ("seed", c_uint64),
                 ("ga_pop", c_int32), ("ga_iters", c_int32), ("precision", c_int32),
-                ("fuse_chains", c_int32)]
+                ("fuse_chains", c_int32), ("exec_mode", c_int32)]
 
 
 class QtnPartial(ctypes.Structure):
@@ -48,7 +48,9 @@ class QtnPlanInfo(ctypes.Structure):
                 ("log2_flops", c_double), ("bytes_per_slice", c_double),
                 ("flops_hoisted", c_double), ("work", c_double), ("prefactor", c_double),
                 ("search_seconds", c_double), ("precision", c_int32),
-                ("f64_below_rank", c_int32)]
+                ("f64_below_rank", c_int32), ("n_programs_wide", c_int32),
+                ("n_launches_wide", c_int32), ("slice_lds_bytes", c_uint32),
+                ("slice_scratch_bytes", c_double)]
 
 
 class QtnKernelTiming(ctypes.Structure):
@@ -223,7 +225,8 @@ class Plan:
 def qtn_plan(n: int, edges: Sequence, p: int, gamma: Sequence[float], beta: Sequence[float],
              bitstrings, k: int = -1, max_rank: int = 0, k_max: int = 24,
              cut_vars: Optional[Sequence[int]] = None, seed: int = 0, ga_pop: int = 11,
-             ga_iters: int = 4, precision: str = "fp64", fuse_chains: bool = True) -> Plan:
+             ga_iters: int = 4, precision: str = "fp64", fuse_chains: bool = True,
+             exec_mode: str = "auto") -> Plan:
     """Builds a plan (host only): network, cut set, order and schedule."""
     L = lib()
     e = _u32(edges).reshape(-1)
@@ -241,6 +244,7 @@ def qtn_plan(n: int, edges: Sequence, p: int, gamma: Sequence[float], beta: Sequ
     opts.ga_iters = ga_iters
     opts.precision = PRECISIONS[precision]
     opts.fuse_chains = 1 if fuse_chains else 0
+    opts.exec_mode = {"auto": -1, "wide": 0, "slice": 1}[exec_mode]
     cv = None
     if cut_vars is not None:
         cv = _u32(cut_vars)

@@ -35,12 +35,13 @@ def _amps(plan, lo, hi):
     return [p.value() for p in plan.contract(lo, hi, _stream())]
 
 
+@pytest.mark.parametrize("mode", ["wide", "slice"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("S", [1, 3, 4])
-def test_tiny_sliced_all_slices(precision, S):
-    print("case n16 p1 k2", precision, "S", S, flush=True)
+def test_tiny_sliced_all_slices(precision, S, mode):
+    print("case n16 p1 k2", precision, "S", S, mode, flush=True)
     inst = workload_instance("qaoa_n16_p1_k2", seed=0)
-    plan = plan_instance(inst, k=2, precision=precision)
+    plan = plan_instance(inst, k=2, precision=precision, exec_mode=mode)
     plan.bind_torch(S)
     cut = plan.cut()
     x = inst.bitstrings[0]
@@ -74,13 +75,14 @@ def test_closed_form_gamma0(precision):
         assert _rel(a, ref, 20) <= TOL[precision]
 
 
+@pytest.mark.parametrize("mode", ["wide", "slice"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_n40_p2_b32_k8_all_amplitudes(precision):
+def test_n40_p2_b32_k8_all_amplitudes(precision, mode):
     """32 bitstrings x 256 slices; the slice sum equals the uncut oracle
     contraction (Eq. (2))."""
-    print("case n40 p2 b32 k8", precision, flush=True)
+    print("case n40 p2 b32 k8", precision, mode, flush=True)
     inst = workload_instance("qaoa_n40_p2_b32_k8", seed=0)
-    plan = plan_instance(inst, k=8, max_rank=18, precision=precision)
+    plan = plan_instance(inst, k=8, max_rank=18, precision=precision, exec_mode=mode)
     plan.bind_torch(100)   # 256 slices in waves of 100: ragged last wave
     amps = _amps(plan, 0, 256)
     order = plan_instance(inst, k=0).order()
@@ -106,6 +108,7 @@ def test_n120_p1_b8(precision):
     inst = workload_instance("qaoa_n120_p1_b8", seed=0)
     plan = plan_instance(inst, k=-1, max_rank=26, precision=precision)
     k = plan.info()["k"]
+    print("k", k, plan.info(), flush=True)
     plan.bind_torch(1 << min(k, 4))
     amps = _amps(plan, 0, 1 << k)
     cut = plan.cut()
@@ -127,14 +130,16 @@ def test_n120_p1_b8(precision):
         assert _rel(a2[b], a2[b + 2], 120) <= TOL[precision]
 
 
-def test_n80_p2_k16_slice_subset():
+@pytest.mark.parametrize("mode", ["wide", "slice"])
+def test_n80_p2_k16_slice_subset(mode):
     """65536 identical-structure slices; a subset of slices against the
     oracle and a 1024-slice range in FP32 against FP64 on the GPU."""
-    print("case n80 p2 k16", flush=True)
+    print("case n80 p2 k16", mode, flush=True)
     inst = workload_instance("qaoa_n80_p2_k16", seed=0)
-    p64 = plan_instance(inst, k=16, max_rank=24, precision="fp64", ga_pop=32, ga_iters=20)
+    p64 = plan_instance(inst, k=16, max_rank=24, precision="fp64", ga_pop=32, ga_iters=20,
+                        exec_mode=mode)
     cut = p64.cut()
-    p32 = plan_instance(inst, cut_vars=cut, precision="fp32")
+    p32 = plan_instance(inst, cut_vars=cut, precision="fp32", exec_mode=mode)
     p64.bind_torch(256)
     p32.bind_torch(256)
     x = inst.bitstrings[0]

@@ -192,3 +192,17 @@ def test_partial_combine_is_error_free():
     c = qtn.qtn_partial_combine(a, b)
     assert c.re == 1e16 + 1.0 and c.re_comp == 1.0 - ((1e16 + 1.0) - 1e16)
     assert (c.re + c.re_comp) - 1e16 == 0.0 or c.re_comp == 1.0
+
+
+@pytest.mark.parametrize("name,k,mode", [("qaoa_n120_p1_b8", -1, "wide"), ("qaoa_n120_p1_b8", 4, "wide"),
+                                         ("qaoa_n120_p1_b8", 4, "slice"),
+                                         ("qaoa_n40_p2_b32_k8", 8, "wide"),
+                                         ("qaoa_n80_p2_k16", 16, "wide"), ("qaoa_n80_p2_k16", 16, "slice")])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_workspace_layout_self_check(name, k, mode, precision):
+    """Layouts for every wave size keep simultaneously live tensors apart
+    (the library verifies this itself and errors otherwise)."""
+    inst = workload_instance(name)
+    P = plan_instance(inst, k=k, max_rank=26, precision=precision, exec_mode=mode)
+    for S in (1, 3, 64, 1 << min(P.info()["k"], 10)):
+        assert P.workspace_bytes(S) > 0
