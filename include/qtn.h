@@ -201,6 +201,16 @@ int qtn_plan_bind_workspace(qtn_plan_t *plan, void *device_ptr, uint64_t bytes,
 int qtn_contract(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi,
                  void *stream, qtn_partial *out);
 
+/*
+ * Enables (1, the default after binding) or disables (0) replay of captured
+ * HIP graphs.  With graphs, the launch sequence of a slice range is captured
+ * on the first qtn_contract for that range, on a library stream that waits
+ * for `stream`, and replayed by later calls with the same range; the
+ * sequence contains no memset nodes.  With graphs off, kernels are launched
+ * on `stream` directly.  Requires a bound workspace.
+ */
+int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
+
 /* Accumulated timing of the streaming step kernel (steps whose output holds
  * at least 2^12 elements per instance), measured with HIP events recorded on
  * the contraction stream around each of its launches. */
@@ -209,6 +219,8 @@ typedef struct {
   double total_ms;   /* summed launch durations                              */
   double alg_bytes;  /* algorithmic bytes: every input read once, output once */
   double alg_flops;  /* real flops of the complex products and sums           */
+  uint64_t dropped;  /* launches whose event pair could not be read           */
+  int32_t last_error;/* HIP error of the last unreadable pair (0 if none)     */
 } qtn_kernel_timing;
 
 /* Enables (1) or disables (0) the timing above and resets its counters.

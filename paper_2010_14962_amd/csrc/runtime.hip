@@ -76,12 +76,30 @@ struct DeviceState {
   size_t ev_used = 0;
   std::vector<double> ev_bytes, ev_flops;
   double t_ms = 0, t_bytes = 0, t_flops = 0;
-  uint64_t t_launches = 0;
+  uint64_t t_launches = 0, t_failed = 0;
+  int t_last_error = 0;
   std::vector<double> step_bytes, step_flops;  // per instance of each step
+  // captured launch sequence of one slice range, replayed while it matches
+  bool use_graphs = true;
+  hipStream_t gstream = nullptr;
+  hipEvent_t gdep = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t g_lo = 0, g_hi = 0;
+  bool g_timing = false;
+  size_t g_ev_used = 0;
+  std::vector<double> g_ev_bytes, g_ev_flops;
 };
+
+static void drop_graph(DeviceState *d) {
+  if (d->gexec) (void)hipGraphExecDestroy(d->gexec);
+  d->gexec = nullptr;
+}
 
 void device_state_free(DeviceState *d) {
   if (!d) return;
+  drop_graph(d);
+  if (d->gdep) (void)hipEventDestroy(d->gdep);
+  if (d->gstream) (void)hipStreamDestroy(d->gstream);
   for (auto e : d->ev) (void)hipEventDestroy(e);
   for (void *p : {(void *)d->leafbuf, (void *)d->tabbuf, (void *)d->stepbuf,
                   (void *)d->progbuf, (void *)d->plistbuf})
@@ -754,6 +772,7 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
   }
+  drop_graph(D);
   D->mode = mode;
   D->ws = (char *)dev_ptr;
   D->ws_bytes = bytes;
@@ -1014,20 +1033,84 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
     return QTN_ESTATE;
   }
   hipStream_t stream = (hipStream_t)stream_v;
-  int rc;
-  if (P->precision == QTN_FP64)
-    rc = run_waves<false>(P, lo, hi, stream);
-  else
-    rc = run_waves<true>(P, lo, hi, stream);
-  if (rc) return rc;
-  HIP_TRY(hipMemcpyAsync(out, P->dev->ws + P->dev->L.partial_off, B * sizeof(qtn_partial),
-                         hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
   DeviceState *D = P->dev;
+  if (D->timing) {
+    // events are created before any capture begins: two per timed launch
+    const ExecPlan &X = P->exec[D->mode];
+    const uint64_t waves = (hi - lo + D->L.S - 1) / D->L.S;
+    const size_t need = (size_t)(2 * waves * X.launches.size());
+    while (D->ev.size() < need) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      // an event is recorded once outside any capture; events whose first
+      // record is a graph node cannot be read back afterwards
+      HIP_TRY(hipEventRecord(e, stream));
+      D->ev.push_back(e);
+    }
+  }
+  auto enqueue = [&](hipStream_t st) {
+    return P->precision == QTN_FP64 ? run_waves<false>(P, lo, hi, st) : run_waves<true>(P, lo, hi, st);
+  };
+  if (D->use_graphs) {
+    // The launch sequence of [lo, hi) is captured once on an internal stream
+    // (ordered after the caller's stream) and replayed while it matches.
+    if (!D->gstream) {
+      HIP_TRY(hipStreamCreateWithFlags(&D->gstream, hipStreamNonBlocking));
+      HIP_TRY(hipEventCreateWithFlags(&D->gdep, hipEventDisableTiming));
+    }
+    if (!D->gexec || D->g_lo != lo || D->g_hi != hi || D->g_timing != D->timing) {
+      drop_graph(D);
+      D->ev_used = 0;
+      D->ev_bytes.clear();
+      D->ev_flops.clear();
+      hipGraph_t graph = nullptr;
+      HIP_TRY(hipStreamBeginCapture(D->gstream, hipStreamCaptureModeThreadLocal));
+      int rc = enqueue(D->gstream);
+      hipError_t ce = hipStreamEndCapture(D->gstream, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+      hipError_t ie = hipGraphInstantiate(&D->gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        D->gexec = nullptr;
+        return hip_fail(ie, "hipGraphInstantiate");
+      }
+      D->g_lo = lo;
+      D->g_hi = hi;
+      D->g_timing = D->timing;
+      D->g_ev_used = D->ev_used;
+      D->g_ev_bytes = D->ev_bytes;
+      D->g_ev_flops = D->ev_flops;
+    }
+    HIP_TRY(hipEventRecord(D->gdep, stream));
+    HIP_TRY(hipStreamWaitEvent(D->gstream, D->gdep, 0));
+    HIP_TRY(hipGraphLaunch(D->gexec, D->gstream));
+    HIP_TRY(hipMemcpyAsync(out, D->ws + D->L.partial_off, B * sizeof(qtn_partial),
+                           hipMemcpyDeviceToHost, D->gstream));
+    HIP_TRY(hipStreamSynchronize(D->gstream));
+    D->ev_used = D->g_ev_used;
+    D->ev_bytes = D->g_ev_bytes;
+    D->ev_flops = D->g_ev_flops;
+  } else {
+    int rc = enqueue(stream);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(out, D->ws + D->L.partial_off, B * sizeof(qtn_partial),
+                           hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+  }
   if (D->timing) {
     for (size_t j = 0; j + 1 < D->ev_used; j += 2) {
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, D->ev[j], D->ev[j + 1]));
+      const hipError_t te = hipEventElapsedTime(&ms, D->ev[j], D->ev[j + 1]);
+      if (te != hipSuccess) {
+        (void)hipGetLastError();
+        ++D->t_failed;
+        D->t_last_error = (int)te;
+        continue;  // a sample that cannot be read is dropped, not an error
+      }
       D->t_ms += ms;
       D->t_bytes += D->ev_bytes[j / 2];
       D->t_flops += D->ev_flops[j / 2];
@@ -1040,6 +1123,16 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
   return QTN_OK;
 }
 
+extern "C" int qtn_plan_set_graphs(qtn_plan_t *P, int enable) {
+  if (!P || !P->dev) {
+    set_error("bind a workspace first");
+    return QTN_ESTATE;
+  }
+  P->dev->use_graphs = enable != 0;
+  drop_graph(P->dev);
+  return QTN_OK;
+}
+
 extern "C" int qtn_plan_set_timing(qtn_plan_t *P, int enable) {
   if (!P || !P->dev) {
     set_error("bind a workspace first");
@@ -1048,7 +1141,8 @@ extern "C" int qtn_plan_set_timing(qtn_plan_t *P, int enable) {
   DeviceState *D = P->dev;
   D->timing = enable != 0;
   D->t_ms = D->t_bytes = D->t_flops = 0;
-  D->t_launches = 0;
+  D->t_launches = D->t_failed = 0;
+  D->t_last_error = 0;
   return QTN_OK;
 }
 
@@ -1062,5 +1156,7 @@ extern "C" int qtn_plan_timing(const qtn_plan_t *P, qtn_kernel_timing *out) {
   out->total_ms = D->t_ms;
   out->alg_bytes = D->t_bytes;
   out->alg_flops = D->t_flops;
+  out->dropped = D->t_failed;
+  out->last_error = D->t_last_error;
   return QTN_OK;
 }

@@ -55,7 +55,7 @@ class QtnPlanInfo(ctypes.Structure):
 
 class QtnKernelTiming(ctypes.Structure):
     _fields_ = [("launches", c_uint64), ("total_ms", c_double), ("alg_bytes", c_double),
-                ("alg_flops", c_double)]
+                ("alg_flops", c_double), ("dropped", c_uint64), ("last_error", c_int32)]
 
 
 class QtnError(RuntimeError):
@@ -70,7 +70,7 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_plan_cut", "qtn_plan_order", "qtn_plan_export", "qtn_plan_kappa",
            "qtn_plan_index_table", "qtn_plan_leaf_values", "qtn_plan_workspace_bytes",
            "qtn_plan_bind_workspace", "qtn_contract", "qtn_partial_combine",
-           "qtn_plan_set_timing", "qtn_plan_timing", "qtn_last_error"]
+           "qtn_plan_set_timing", "qtn_plan_timing", "qtn_plan_set_graphs", "qtn_last_error"]
 
 
 def lib():
@@ -101,6 +101,7 @@ def lib():
     L.qtn_contract.argtypes = [c_void_p, c_uint64, c_uint64, c_void_p, POINTER(QtnPartial)]
     L.qtn_partial_combine.argtypes = [POINTER(QtnPartial), POINTER(QtnPartial), POINTER(QtnPartial)]
     L.qtn_plan_set_timing.argtypes = [c_void_p, c_int32]
+    L.qtn_plan_set_graphs.argtypes = [c_void_p, c_int32]
     L.qtn_plan_timing.argtypes = [c_void_p, POINTER(QtnKernelTiming)]
     L.qtn_last_error.argtypes = []
     L.qtn_last_error.restype = c_char_p
@@ -207,6 +208,9 @@ class Plan:
         self.bind_workspace(ws.data_ptr(), nbytes, slices_per_wave)
         self._workspace = ws
         return ws
+
+    def set_graphs(self, enable: bool = True):
+        _check(lib().qtn_plan_set_graphs(self._h, 1 if enable else 0))
 
     def set_timing(self, enable: bool = True):
         _check(lib().qtn_plan_set_timing(self._h, 1 if enable else 0))

@@ -179,3 +179,30 @@ def test_degenerate_all_variables_cut():
         sv = Q.statevector_amplitude(6, inst.edges, 1, inst.gamma, inst.beta, inst.bitstrings[b])
         assert _rel(amps[b], sv, 6) <= 1e-12
     assert [p.value() for p in plan.contract(5, 5)] == [0j, 0j]
+
+
+@pytest.mark.parametrize("mode", ["wide", "slice"])
+def test_graph_replays_match_eager(mode):
+    """Captured launch sequences replayed several times, with unrelated eager
+    work and synchronisations between replays, reproduce the eager launches
+    bit for bit."""
+    inst = workload_instance("qaoa_n40_p2_b32_k8", seed=2)
+    eager = plan_instance(inst, k=8, precision="fp32", exec_mode=mode)
+    eager.bind_torch(64)
+    eager.set_graphs(False)
+    ref = [(p.re, p.im, p.re_comp, p.im_comp) for p in eager.contract(0, 256, _stream())]
+    g = plan_instance(inst, cut_vars=eager.cut(), precision="fp32", exec_mode=mode)
+    g.bind_torch(64)
+    g.set_graphs(True)
+    x = torch.randn(512, 512, device="cuda")
+    for rep in range(4):
+        got = [(p.re, p.im, p.re_comp, p.im_comp) for p in g.contract(0, 256, _stream())]
+        assert got == ref, rep
+        y = (x @ x).sum()            # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+        eager.contract(0, 17, _stream())
+    # a different range re-captures and still matches eager
+    part = [(p.re, p.im) for p in g.contract(3, 200, _stream())]
+    ref2 = [(p.re, p.im) for p in eager.contract(3, 200, _stream())]
+    assert part == ref2
