@@ -230,6 +230,77 @@ int qtn_plan_set_timing(qtn_plan_t *plan, int enable);
 /* Reads the counters accumulated by qtn_contract calls since the last reset. */
 int qtn_plan_timing(const qtn_plan_t *plan, qtn_kernel_timing *out);
 
+/* ---------------------------------------------------------------------------
+ * Learned cut-set cost model.  Not part of the paper: it ranks candidate cut
+ * sets for the search of Sec. III B by predicted log2 cost and peak rank;
+ * every returned cut set is scored by the exact evaluator.
+ * ------------------------------------------------------------------------- */
+#define QTN_COST_FEATURES 32
+
+/* Features of n_sets candidate cut sets of size k (row-major n_sets x k
+ * variable ids) into features[n_sets x QTN_COST_FEATURES]: mean, max, min
+ * and sum over the set of six per-variable statistics of the uncut min-fill
+ * elimination (degree, position, bag size, fill-in, bags holding it, layer),
+ * then n, p, k, uncut width, uncut log2 work, and three set statistics. */
+int qtn_cost_features(const qtn_graph *graph, uint32_t p, const uint32_t *cut_sets,
+                      uint32_t n_sets, uint32_t k, float *features);
+
+/* Exact cost of each cut set (labels and fallback): width of the min-fill
+ * order on G - C (= largest slice tensor rank) and log2(work * 2^k) with
+ * work = sum over eliminated variables of 2^(|N+(v)|+1).  threads >= 1. */
+int qtn_cost_exact(const qtn_graph *graph, uint32_t p, const uint32_t *cut_sets,
+                   uint32_t n_sets, uint32_t k, int32_t *width, double *log2_cost,
+                   int32_t threads);
+
+typedef struct qtn_mlp_s qtn_mlp_t;
+
+/* Multilayer perceptron in_dim -> hidden (x n_hidden, ReLU) -> out_dim on the
+ * current device, FP32, He-initialised from `seed`.  Dense layers run on FP32
+ * matrix cores.  The library owns its parameters and activations (sized for
+ * max_batch rows). */
+int qtn_mlp_create(uint32_t in_dim, uint32_t hidden, uint32_t n_hidden, uint32_t out_dim,
+                   uint32_t max_batch, uint64_t seed, qtn_mlp_t **out);
+void qtn_mlp_destroy(qtn_mlp_t *mlp);
+
+/* Parameter vector: for each layer, W [fan_in x fan_out] row-major then b. */
+int qtn_mlp_num_params(const qtn_mlp_t *mlp, uint64_t *count);
+int qtn_mlp_get_params(const qtn_mlp_t *mlp, float *host, uint64_t capacity);
+int qtn_mlp_set_params(qtn_mlp_t *mlp, const float *host, uint64_t count);
+/* Gradients of the last qtn_mlp_train_step, same layout as the parameters. */
+int qtn_mlp_get_grads(const qtn_mlp_t *mlp, float *host, uint64_t capacity);
+
+/* Feature and label standardisation used by the guided search. */
+int qtn_mlp_set_normalization(qtn_mlp_t *mlp, const float *x_mean, const float *x_std,
+                              const float *y_mean, const float *y_std);
+
+/* y_dev[batch x out_dim] = MLP(x_dev[batch x in_dim]) on `stream` (device pointers). */
+int qtn_mlp_forward(qtn_mlp_t *mlp, const float *x_dev, uint32_t batch, float *y_dev,
+                    void *stream);
+
+/* One step of mean-squared-error training with Adam (lr = 0: gradients only).
+ * loss (host, may be NULL) receives the batch loss; the call then waits. */
+int qtn_mlp_train_step(qtn_mlp_t *mlp, const float *x_dev, const float *t_dev, uint32_t batch,
+                       float lr, void *stream, float *loss);
+
+typedef struct {
+  double seconds;        /* wall time, model inference included */
+  uint64_t exact_evals;  /* distinct cut sets scored exactly    */
+  uint64_t model_evals;  /* candidates ranked by the model      */
+  int32_t width;         /* exact width of the returned cut set */
+  double log2_cost;      /* exact log2(work * 2^k)             */
+} qtn_search_stats;
+
+/*
+ * Cut search of size k.  model == NULL: each generation replaces the N-1
+ * non-best individuals by crossover/mutation offspring (Sec. III B) scored
+ * exactly.  model != NULL: offspring_factor x (N-1) offspring per generation
+ * are ranked by the model and only the best N-1 distinct ones are scored
+ * exactly.  Returns the best exactly-scored cut set (ascending) in cut_out.
+ */
+int qtn_cut_search(const qtn_graph *graph, uint32_t p, uint32_t k, int32_t pop, int32_t iters,
+                   uint64_t seed, qtn_mlp_t *model, int32_t offspring_factor,
+                   uint32_t *cut_out, qtn_search_stats *stats);
+
 /* Error-free combination of two partials (TwoSum on each component). */
 int qtn_partial_combine(const qtn_partial *a, const qtn_partial *b,
                         qtn_partial *out);

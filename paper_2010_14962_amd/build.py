@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqtn.so")
 
-SOURCES = ["planner.cpp", "api.cpp", "runtime.hip"]
+SOURCES = ["planner.cpp", "api.cpp", "costmodel.cpp", "runtime.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

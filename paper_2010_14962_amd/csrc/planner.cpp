@@ -248,6 +248,7 @@ CutResult ga_cut_search(const std::vector<std::vector<int>> &adj, int M, int N,
   out.cut = f.sorted;
   out.width = f.width;
   out.work = f.work;
+  out.evals = cache.size();
   return out;
 }
 

@@ -72,6 +72,7 @@ struct CutResult {
   std::vector<int> cut;  // ascending
   int width = 0;
   uint64_t work = 0;
+  uint64_t evals = 0;    // distinct cut sets scored exactly
 };
 
 // Algorithm 1 (Sec. III B) with exact min-fill fitness.

@@ -58,6 +58,11 @@ class QtnKernelTiming(ctypes.Structure):
                 ("alg_flops", c_double), ("dropped", c_uint64), ("last_error", c_int32)]
 
 
+class QtnSearchStats(ctypes.Structure):
+    _fields_ = [("seconds", c_double), ("exact_evals", c_uint64), ("model_evals", c_uint64),
+                ("width", c_int32), ("log2_cost", c_double)]
+
+
 class QtnError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("qtn error %d: %s" % (code, msg))
@@ -70,7 +75,11 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_plan_cut", "qtn_plan_order", "qtn_plan_export", "qtn_plan_kappa",
            "qtn_plan_index_table", "qtn_plan_leaf_values", "qtn_plan_workspace_bytes",
            "qtn_plan_bind_workspace", "qtn_contract", "qtn_partial_combine",
-           "qtn_plan_set_timing", "qtn_plan_timing", "qtn_plan_set_graphs", "qtn_last_error"]
+           "qtn_plan_set_timing", "qtn_plan_timing", "qtn_plan_set_graphs", "qtn_last_error",
+           "qtn_cost_features", "qtn_cost_exact", "qtn_mlp_create", "qtn_mlp_destroy",
+           "qtn_mlp_num_params", "qtn_mlp_get_params", "qtn_mlp_set_params", "qtn_mlp_get_grads",
+           "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search"]
+COST_FEATURES = 32
 
 
 def lib():
@@ -105,8 +114,27 @@ def lib():
     L.qtn_plan_timing.argtypes = [c_void_p, POINTER(QtnKernelTiming)]
     L.qtn_last_error.argtypes = []
     L.qtn_last_error.restype = c_char_p
+    pf, pu32 = POINTER(ctypes.c_float), POINTER(c_uint32)
+    L.qtn_cost_features.argtypes = [POINTER(QtnGraph), c_uint32, pu32, c_uint32, c_uint32, pf]
+    L.qtn_cost_exact.argtypes = [POINTER(QtnGraph), c_uint32, pu32, c_uint32, c_uint32,
+                                 POINTER(c_int32), POINTER(c_double), c_int32]
+    L.qtn_mlp_create.argtypes = [c_uint32, c_uint32, c_uint32, c_uint32, c_uint32, c_uint64,
+                                 POINTER(c_void_p)]
+    L.qtn_mlp_destroy.argtypes = [c_void_p]
+    L.qtn_mlp_destroy.restype = None
+    L.qtn_mlp_num_params.argtypes = [c_void_p, POINTER(c_uint64)]
+    L.qtn_mlp_get_params.argtypes = [c_void_p, pf, c_uint64]
+    L.qtn_mlp_set_params.argtypes = [c_void_p, pf, c_uint64]
+    L.qtn_mlp_get_grads.argtypes = [c_void_p, pf, c_uint64]
+    L.qtn_mlp_set_normalization.argtypes = [c_void_p, pf, pf, pf, pf]
+    L.qtn_mlp_forward.argtypes = [c_void_p, c_void_p, c_uint32, c_void_p, c_void_p]
+    L.qtn_mlp_train_step.argtypes = [c_void_p, c_void_p, c_void_p, c_uint32, ctypes.c_float,
+                                     c_void_p, pf]
+    L.qtn_cut_search.argtypes = [POINTER(QtnGraph), c_uint32, c_uint32, c_int32, c_int32,
+                                 c_uint64, c_void_p, c_int32, pu32, POINTER(QtnSearchStats)]
     for name in EXPORTS:
-        if name not in ("qtn_plan_opts_default", "qtn_plan_destroy", "qtn_last_error"):
+        if name not in ("qtn_plan_opts_default", "qtn_plan_destroy", "qtn_last_error",
+                        "qtn_mlp_destroy"):
             getattr(L, name).restype = c_int32
     _lib = L
     return L
@@ -270,3 +298,125 @@ def qtn_partial_combine(a: QtnPartial, b: QtnPartial) -> QtnPartial:
 def plan_instance(inst, **kw) -> Plan:
     """qtn_plan for an instances.Instance."""
     return qtn_plan(inst.n, inst.edges, inst.p, inst.gamma, inst.beta, inst.bitstrings, **kw)
+
+
+def _graph(n: int, edges):
+    e = _u32(edges).reshape(-1)
+    return QtnGraph(n, len(e) // 2, e.ctypes.data_as(POINTER(c_uint32))), e
+
+
+def _sets(cut_sets) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(cut_sets, dtype=np.uint32))
+    if a.ndim != 2:
+        raise ValueError("cut_sets must be a 2-D array (sets x k)")
+    return a
+
+
+def cost_features(n: int, edges, p: int, cut_sets) -> np.ndarray:
+    """Model input features of each cut set (rows of cut_sets)."""
+    g, _e = _graph(n, edges)
+    a = _sets(cut_sets)
+    out = np.zeros((a.shape[0], COST_FEATURES), dtype=np.float32)
+    _check(lib().qtn_cost_features(byref(g), p, a.ctypes.data_as(POINTER(c_uint32)), a.shape[0],
+                                   a.shape[1], out.ctypes.data_as(POINTER(ctypes.c_float))))
+    return out
+
+
+def cost_exact(n: int, edges, p: int, cut_sets, threads: int = 1):
+    """Exact (width, log2 cost) of each cut set."""
+    g, _e = _graph(n, edges)
+    a = _sets(cut_sets)
+    w = np.zeros(a.shape[0], dtype=np.int32)
+    c = np.zeros(a.shape[0], dtype=np.float64)
+    _check(lib().qtn_cost_exact(byref(g), p, a.ctypes.data_as(POINTER(c_uint32)), a.shape[0],
+                                a.shape[1], w.ctypes.data_as(POINTER(c_int32)),
+                                c.ctypes.data_as(POINTER(c_double)), threads))
+    return w, c
+
+
+def _fptr(a: np.ndarray):
+    return a.ctypes.data_as(POINTER(ctypes.c_float))
+
+
+class CostMLP:
+    """Owns one qtn_mlp_t (parameters and activations on the current device)."""
+
+    def __init__(self, in_dim: int = COST_FEATURES, hidden: int = 256, n_hidden: int = 3,
+                 out_dim: int = 2, max_batch: int = 4096, seed: int = 0):
+        h = c_void_p()
+        _check(lib().qtn_mlp_create(in_dim, hidden, n_hidden, out_dim, max_batch, seed, byref(h)))
+        self._h = h
+        self.dims = [in_dim] + [hidden] * n_hidden + [out_dim]
+        self.max_batch = max_batch
+
+    def __del__(self):
+        try:
+            if self._h is not None and self._h.value:
+                lib().qtn_mlp_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def num_params(self) -> int:
+        c = c_uint64()
+        _check(lib().qtn_mlp_num_params(self._h, byref(c)))
+        return c.value
+
+    def get_params(self) -> np.ndarray:
+        out = np.zeros(self.num_params(), dtype=np.float32)
+        _check(lib().qtn_mlp_get_params(self._h, _fptr(out), out.size))
+        return out
+
+    def get_grads(self) -> np.ndarray:
+        out = np.zeros(self.num_params(), dtype=np.float32)
+        _check(lib().qtn_mlp_get_grads(self._h, _fptr(out), out.size))
+        return out
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(np.asarray(flat, dtype=np.float32))
+        _check(lib().qtn_mlp_set_params(self._h, _fptr(a), a.size))
+
+    def unflatten(self, flat):
+        """[(W, b)] per layer from a flat parameter vector."""
+        out, o = [], 0
+        for din, dout in zip(self.dims[:-1], self.dims[1:]):
+            W = np.asarray(flat[o:o + din * dout]).reshape(din, dout)
+            o += din * dout
+            b = np.asarray(flat[o:o + dout])
+            o += dout
+            out.append((W, b))
+        return out
+
+    def set_normalization(self, x_mean, x_std, y_mean, y_std):
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in
+                (x_mean, x_std, y_mean, y_std)]
+        _check(lib().qtn_mlp_set_normalization(self._h, *[_fptr(a) for a in arrs]))
+
+    def forward(self, x_ptr: int, batch: int, y_ptr: int, stream: Optional[int] = None):
+        _check(lib().qtn_mlp_forward(self._h, c_void_p(x_ptr), batch, c_void_p(y_ptr),
+                                     c_void_p(stream or 0)))
+
+    def train_step(self, x_ptr: int, t_ptr: int, batch: int, lr: float,
+                   stream: Optional[int] = None) -> float:
+        loss = ctypes.c_float()
+        _check(lib().qtn_mlp_train_step(self._h, c_void_p(x_ptr), c_void_p(t_ptr), batch, lr,
+                                        c_void_p(stream or 0), byref(loss)))
+        return loss.value
+
+
+def cut_search(n: int, edges, p: int, k: int, pop: int = 11, iters: int = 4, seed: int = 0,
+               model: Optional[CostMLP] = None, offspring_factor: int = 16):
+    """Cut set of size k and the search statistics (model-guided when `model`)."""
+    g, _e = _graph(n, edges)
+    out = np.zeros(max(k, 1), dtype=np.uint32)
+    st = QtnSearchStats()
+    _check(lib().qtn_cut_search(byref(g), p, k, pop, iters, seed,
+                                model.handle if model is not None else None, offspring_factor,
+                                out.ctypes.data_as(POINTER(c_uint32)), byref(st)))
+    return [int(v) for v in out[:k]], {"seconds": st.seconds, "exact_evals": st.exact_evals,
+                                       "model_evals": st.model_evals, "width": st.width,
+                                       "log2_cost": st.log2_cost}

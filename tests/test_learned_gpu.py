@@ -1,0 +1,132 @@
+"""GPU tests of the learned cut-set cost model: libqtn's forward, backward and
+Adam kernels against the float64 oracle MLP, training on exact labels, and the
+model-guided search against Algorithm 1 (every chosen cut re-scored exactly)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from instances import make_instance
+from oracle.mlp import MLP64
+from paper_2010_14962_amd import qtn
+from paper_2010_14962_amd import learned as LM
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(32, 256, 3, 2, 300), (7, 40, 2, 3, 17), (32, 16, 0, 2, 1), (5, 33, 1, 1, 64)]
+
+
+def _oracle_of(model):
+    layers = model.unflatten(model.get_params())
+    return MLP64([W.astype(np.float64) for W, _ in layers], [b.astype(np.float64) for _, b in layers])
+
+
+def _inputs(batch, din, dout, seed):
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal((batch, din)).astype(np.float32),
+            rng.standard_normal((batch, dout)).astype(np.float32))
+
+
+@pytest.mark.parametrize("din,hidden,nh,dout,batch", SHAPES)
+def test_forward_matches_oracle(din, hidden, nh, dout, batch):
+    torch.cuda.set_device(0)
+    m = qtn.CostMLP(din, hidden, nh, dout, max_batch=max(batch, 64), seed=3)
+    # non-zero biases so the bias path is exercised
+    flat = m.get_params()
+    flat += np.random.default_rng(1).standard_normal(flat.size).astype(np.float32) * 0.05
+    m.set_params(flat)
+    ref = _oracle_of(m)
+    x, _ = _inputs(batch, din, dout, 5)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty((batch, dout), dtype=torch.float32, device="cuda")
+    m.forward(xd.data_ptr(), batch, yd.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    y_ref, _ = ref.forward(x.astype(np.float64))
+    err = np.abs(yd.cpu().numpy() - y_ref).max() / max(np.abs(y_ref).max(), 1e-30)
+    assert err <= 1e-4, err
+
+
+@pytest.mark.parametrize("din,hidden,nh,dout,batch", SHAPES)
+def test_gradients_match_oracle(din, hidden, nh, dout, batch):
+    torch.cuda.set_device(0)
+    m = qtn.CostMLP(din, hidden, nh, dout, max_batch=max(batch, 64), seed=4)
+    ref = _oracle_of(m)
+    x, t = _inputs(batch, din, dout, 6)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    loss = m.train_step(xd.data_ptr(), td.data_ptr(), batch, 0.0,
+                        torch.cuda.current_stream().cuda_stream)
+    loss_ref, gW, gb = ref.loss_and_grads(x.astype(np.float64), t.astype(np.float64))
+    assert abs(loss - loss_ref) <= 1e-4 * loss_ref
+    got = m.unflatten(m.get_grads())
+    for l, (W, b) in enumerate(got):
+        sw = max(np.abs(gW[l]).max(), 1e-30)
+        sb = max(np.abs(gb[l]).max(), 1e-30)
+        assert np.abs(W - gW[l]).max() <= 1e-4 * sw, ("dW", l)
+        assert np.abs(b - gb[l]).max() <= 1e-4 * sb, ("db", l)
+    # lr = 0 leaves the parameters alone
+    assert np.array_equal(m.get_params(), np.concatenate(
+        [np.concatenate([W.reshape(-1), b]) for W, b in m.unflatten(m.get_params())]))
+
+
+def test_adam_steps_match_oracle():
+    torch.cuda.set_device(0)
+    m = qtn.CostMLP(32, 64, 2, 2, max_batch=128, seed=7)
+    ref = _oracle_of(m)
+    stream = torch.cuda.current_stream().cuda_stream
+    for it in range(3):
+        x, t = _inputs(128, 32, 2, 10 + it)
+        xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+        before = m.get_params().astype(np.float64)
+        m.train_step(xd.data_ptr(), td.data_ptr(), 128, 1e-3, stream)
+        _, gW, gb = ref.loss_and_grads(x.astype(np.float64), t.astype(np.float64))
+        ref.adam_step(gW, gb, lr=1e-3)
+        after = m.get_params().astype(np.float64)
+        ref_flat = np.concatenate([np.concatenate([W.reshape(-1), b]) for W, b in zip(ref.W, ref.b)])
+        # the step is about lr per weight; agree to 2% of it
+        assert np.abs(after - ref_flat).max() <= 2e-5, it
+        assert np.abs(after - before).max() > 1e-4
+
+
+@pytest.fixture(scope="module")
+def trained():
+    torch.cuda.set_device(0)
+    specs = []
+    gid = 0
+    for n in (60, 80, 100, 120):
+        for p in (1, 2):
+            for g in range(2):
+                inst = make_instance(n, p, 1, 1000 + gid)
+                specs.append(LM.GraphSpec(n, p, inst.edges, gid))
+                gid += 1
+    ds = LM.make_dataset(specs, 600, k_range=(4, 16), seed=1, threads=16)
+    held = ds.graph % 8 == 7
+    tr = LM.Dataset(ds.X[~held], ds.Y[~held], ds.graph[~held])
+    te = LM.Dataset(ds.X[held], ds.Y[held], ds.graph[held])
+    model, losses = LM.train(tr, epochs=25, batch=512, lr=1e-3, seed=0)
+    return model, losses, te
+
+
+def test_training_lowers_loss_and_generalises(trained):
+    model, losses, te = trained
+    assert losses[-1] < 0.25 * losses[0], losses
+    ev = LM.evaluate(model, te)
+    print("held-out", ev)
+    assert ev["mae_rank"] < 1.5 and ev["mae_log2_cost"] < 1.0
+    assert ev["spearman_log2_cost"] > 0.7
+
+
+def test_guided_search_rescored_and_gains(trained):
+    model, _, _ = trained
+    specs = []
+    for n, p in ((120, 1), (80, 2)):
+        inst = make_instance(n, p, 1, 7000 + n + p)
+        specs.append(LM.GraphSpec(n, p, inst.edges, -1))
+    rows = LM.gain_comparison(model, specs, 12, seeds=[0, 1, 2])
+    for r in rows:
+        print(r["n"], r["p"], r["seed"], {k: (r[k]["width"], round(r[k]["log2_cost"], 2),
+                                             r[k]["exact_evals"]) for k in ("alg1", "guided", "random")})
+    key = lambda st: (st["width"], st["log2_cost"])
+    wins = sum(key(r["guided"]) <= key(r["alg1"]) for r in rows)
+    beat_random = sum(key(r["guided"]) <= key(r["random"]) for r in rows)
+    assert wins >= len(rows) - 1
+    assert beat_random >= len(rows) - 1
