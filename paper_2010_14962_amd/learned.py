@@ -148,19 +148,29 @@ def predict(model: "qtn.CostMLP", X: np.ndarray, device: str = "cuda") -> np.nda
     return out.cpu().numpy() * norm.y_std + norm.y_mean
 
 
+K_FEATURE = 26      # column of k in the feature vector
+
+
 def evaluate(model, ds: Dataset) -> dict:
-    """MAE of peak rank and log2 cost, and the mean per-graph Spearman rho of
-    the predicted log2 cost."""
+    """MAE of peak rank and log2 cost, the mean per-graph Spearman rho of the
+    predicted log2 cost, and the same rho within (graph, k) groups (the
+    ranking a search of fixed k relies on)."""
     from scipy.stats import spearmanr
     P = predict(model, ds.X)
-    rho = []
+    rho, rho_k = [], []
     for gid in np.unique(ds.graph):
         m = ds.graph == gid
         if m.sum() > 2:
             rho.append(spearmanr(P[m, 1], ds.Y[m, 1]).statistic)
+        for k in np.unique(ds.X[m, K_FEATURE]):
+            mk = m & (ds.X[:, K_FEATURE] == k)
+            if mk.sum() > 10 and np.ptp(ds.Y[mk, 1]) > 0:
+                rho_k.append(spearmanr(P[mk, 1], ds.Y[mk, 1]).statistic)
     return {"mae_rank": float(np.abs(P[:, 0] - ds.Y[:, 0]).mean()),
             "mae_log2_cost": float(np.abs(P[:, 1] - ds.Y[:, 1]).mean()),
-            "spearman_log2_cost": float(np.mean(rho)), "rows": int(ds.X.shape[0])}
+            "spearman_log2_cost": float(np.mean(rho)),
+            "spearman_log2_cost_fixed_k": float(np.mean(rho_k)) if rho_k else None,
+            "rows": int(ds.X.shape[0])}
 
 
 def random_search(spec: GraphSpec, k: int, count: int, seed: int, threads: int = 1):
@@ -178,9 +188,12 @@ def random_search(spec: GraphSpec, k: int, count: int, seed: int, threads: int =
 
 def gain_comparison(model, specs: Sequence[GraphSpec], k: int, seeds: Sequence[int],
                     pop: int = 11, iters: int = 4, factor: int = 16) -> List[dict]:
-    """(i) Algorithm 1 with exact fitness, (ii) model-guided search with
-    `factor` x more offspring per generation, (iii) random sets with as many
-    exact evaluations as (ii).  Every reported cost is an exact re-score."""
+    """(i) Algorithm 1 with exact fitness; (ii) model-guided search with
+    `factor` x more offspring per generation, the model keeping the best N for
+    exact scoring; (ii') the same loop with factor 1, where every offspring is
+    scored and the model decides nothing (the model's own contribution is
+    (ii) against (ii')); (iii) random sets with as many exact evaluations as
+    (ii).  Every reported cost is an exact re-score."""
     rows = []
     for spec in specs:
         for s in seeds:
@@ -189,9 +202,11 @@ def gain_comparison(model, specs: Sequence[GraphSpec], k: int, seeds: Sequence[i
                                        offspring_factor=factor)
             w2, c2 = qtn.cost_exact(spec.n, spec.edges, spec.p, np.array([cut2], dtype=np.uint32))
             assert int(w2[0]) == st2["width"] and float(c2[0]) == st2["log2_cost"]
+            _, st2b = qtn.cut_search(spec.n, spec.edges, spec.p, k, pop, iters, s, model=model,
+                                     offspring_factor=1)
             cut3, st3 = random_search(spec, k, int(st2["exact_evals"]), s)
             rows.append({"n": spec.n, "p": spec.p, "graph": spec.graph_id, "k": k, "seed": s,
-                         "alg1": st1, "guided": st2, "random": st3})
+                         "alg1": st1, "guided": st2, "unscreened": st2b, "random": st3})
     return rows
 
 

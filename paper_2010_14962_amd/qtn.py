@@ -89,6 +89,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("libqtn.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    # torch supplies device memory and streams; its HIP runtime is brought up
+    # before libqtn's code object registers, the order every caller relies on
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     L.qtn_plan_opts_default.argtypes = [POINTER(QtnPlanOpts)]
     L.qtn_plan_opts_default.restype = None
