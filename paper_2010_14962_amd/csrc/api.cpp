@@ -146,6 +146,22 @@ extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
     P->exec_mode = opts.exec_mode;
     P->exec[MODE_WIDE] = build_exec(P->sched, MODE_WIDE, kLdsBudget);
     P->exec[MODE_SLICE] = build_exec(P->sched, MODE_SLICE, kLdsBudget);
+    if (const char *e = std::getenv("QTN_PLAN_REPORT"); e && e[0] == '1') {
+      // launch structure of both execution modes, for tuning
+      for (int m = 0; m < 2; ++m) {
+        const ExecPlan &X = P->exec[m];
+        std::fprintf(stderr, "qtn plan: mode %d, %zu programs, %zu launches, program LDS %u B\n", m,
+                     X.programs.size(), X.launches.size(), X.lds_bytes);
+        for (size_t i = 0; i < X.programs.size(); ++i) {
+          const Program &pr = X.programs[i];
+          int nleaf = 0;
+          for (int st : pr.steps)
+            for (int in : P->sched.steps[st].in) nleaf += P->sched.tensors[in].leaf ? 1 : 0;
+          std::fprintf(stderr, "  program %zu: %zu steps, %zu of %d factors staged, LDS %u B\n", i,
+                       pr.steps.size(), pr.staged.size(), nleaf, pr.lds_bytes);
+        }
+      }
+    }
     if (opts.max_rank > 0 && P->sched.width > opts.max_rank) {
       delete P;
       return fail(QTN_ERANK, "cut set does not meet max_rank");

@@ -603,8 +603,17 @@ ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget) {
     lds.limit = lds_budget;
     std::vector<char> mine(nt, 0);
     for (int st : P.steps) mine[s.steps[st].out] = 1;
+    // LDS intervals of the intermediates: bytes [off, off+size) during the
+    // steps at positions t0..t1 of the program
+    struct Iv {
+      uint64_t off, size;
+      int t0, t1;
+    };
+    std::vector<Iv> ivs;
+    std::vector<int> iv_of(nt, -1);
     int slots = 0;
-    for (int st : P.steps) {
+    for (size_t si = 0; si < P.steps.size(); ++si) {
+      const int st = P.steps[si];
       const int o = s.steps[st].out;
       if (o != P.root) {
         const uint64_t lbytes = (uint64_t)16 << s.tensors[o].rank();
@@ -612,6 +621,8 @@ ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget) {
         if (lds.alloc((lbytes + 15) & ~uint64_t(15), off)) {
           x.loc[o] = LOC_LDS;
           x.off[o] = off;
+          iv_of[o] = (int)ivs.size();
+          ivs.push_back({off, (lbytes + 15) & ~uint64_t(15), (int)si, (int)si});
         } else if (scratch_ok) {
           const uint64_t sb = (((uint64_t)elem_bytes(s.tensors[o]) << s.tensors[o].rank()) + 255) & ~uint64_t(255);
           scr.alloc(sb, off);
@@ -625,13 +636,43 @@ ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget) {
       for (int i : s.steps[st].in) {
         if (!mine[i] || consumer[i] != st) continue;
         const Tensor &t = s.tensors[i];
-        if (x.loc[i] == LOC_LDS)
+        if (x.loc[i] == LOC_LDS) {
           lds.release(x.off[i], (((uint64_t)16 << t.rank()) + 15) & ~uint64_t(15));
-        else if (x.loc[i] == LOC_SCRATCH)
+          ivs[iv_of[i]].t1 = (int)si;
+        } else if (x.loc[i] == LOC_SCRATCH) {
           scr.release(x.off[i], (((uint64_t)elem_bytes(t) << t.rank()) + 255) & ~uint64_t(255));
+        }
       }
     }
-    P.lds_bytes = (uint32_t)lds.peak;
+    // Gate factors the program reads are staged in LDS at its start where
+    // they fit: each is live from the start to its consuming step.
+    uint64_t top = lds.peak;
+    for (size_t si = 0; si < P.steps.size(); ++si)
+      for (int i : s.steps[P.steps[si]].in) {
+        if (!s.tensors[i].leaf) continue;
+        const uint64_t size = (uint64_t)16 << s.tensors[i].rank();
+        std::vector<uint64_t> cand{0};
+        for (const Iv &v : ivs)
+          if (v.t0 <= (int)si) cand.push_back(v.off + v.size);
+        std::sort(cand.begin(), cand.end());
+        for (uint64_t c : cand) {
+          if (c + size > lds_budget) break;
+          bool ok = true;
+          for (const Iv &v : ivs)
+            if (v.t0 <= (int)si && c < v.off + v.size && v.off < c + size) {
+              ok = false;
+              break;
+            }
+          if (!ok) continue;
+          ivs.push_back({c, size, -1, (int)si});
+          x.loc[i] = LOC_LDS;
+          x.off[i] = c;
+          P.staged.push_back(i);
+          top = std::max(top, c + size);
+          break;
+        }
+      }
+    P.lds_bytes = (uint32_t)top;
     P.scratch_bytes = scr.peak;
     P.nslots = slots;
   };

@@ -151,6 +151,7 @@ struct Program {
   uint32_t lds_bytes = 0;       // LDS tensors (complex128)
   uint64_t scratch_bytes = 0;   // per-workgroup global scratch
   int nslots = 0;               // program-local exponent slots
+  std::vector<int> staged;      // gate factors copied to LDS at program start
 };
 
 struct LaunchGroup {

@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -38,6 +40,10 @@ struct OpDesc {
   uint32_t off;           // LDS / scratch byte offset
   int slot;               // LDS / scratch: exponent slot
   uint32_t cvary;         // index depends on the output element
+  uint32_t pc;            // popcount of the output part of the mask
+  uint32_t nlo;           // popcount of its lowest 8 bits
+  uint32_t nkv;           // popcount of the kappa part of the mask
+  uint32_t mask;          // operand bits over the step index kappa:c
 };
 
 struct PStep {
@@ -46,11 +52,21 @@ struct PStep {
   int nin, rC, nk;
   int nvary;              // in[0..nvary) vary with the output element
   int nf32;               // of those, in[0..nf32) are stored as complex64
+  uint32_t tiled_lds;     // > 0: run as step_tiled with this much LDS
 };
 
 struct ProgDesc {
   uint32_t step0, nsteps;
   uint32_t bdep, sdep;
+  uint32_t stage0, nstage;    // gate factors staged in LDS at program start
+};
+
+// One gate factor a program stages in LDS: the variant of instance (b, s)
+// is base + b * bstride + pext(s, selmask) * vsize, count complex128 values.
+struct LeafStage {
+  const double2 *base;
+  uint64_t bstride, vsize;
+  uint32_t selmask, count, lds_off, pad;
 };
 
 struct DeviceState {
@@ -61,6 +77,7 @@ struct DeviceState {
   PStep *stepbuf = nullptr;       // program steps, contiguous per program
   ProgDesc *progbuf = nullptr;
   int *plistbuf = nullptr;        // program ids of every launch group
+  LeafStage *stagebuf = nullptr;  // staged gate factors of every program
   std::vector<uint64_t> leaf_elem_off;
   std::vector<std::vector<uint64_t>> tab_off;
   std::vector<PStep> steps;       // one descriptor per schedule step (host copy)
@@ -102,7 +119,7 @@ void device_state_free(DeviceState *d) {
   if (d->gstream) (void)hipStreamDestroy(d->gstream);
   for (auto e : d->ev) (void)hipEventDestroy(e);
   for (void *p : {(void *)d->leafbuf, (void *)d->tabbuf, (void *)d->stepbuf,
-                  (void *)d->progbuf, (void *)d->plistbuf})
+                  (void *)d->progbuf, (void *)d->plistbuf, (void *)d->stagebuf})
     if (p) (void)hipFree(p);
   delete d;
 }
@@ -200,6 +217,10 @@ __device__ __forceinline__ uint64_t cpart(const OpDesc &o, uint32_t c) {
 // ---------------------------------------------------------------------------
 // Workgroup programs
 // ---------------------------------------------------------------------------
+// Dynamic LDS of the program kernel: tensors | 256 partial sums | exponent
+// slots | 4 reduction words.
+extern __shared__ __align__(16) char wg_smem[];
+
 struct WgCtx {
   double2 *lds;           // program tensors (complex128)
   double2 *red;           // 256 partial sums
@@ -209,17 +230,26 @@ struct WgCtx {
   char *scratch;          // this workgroup's global scratch
 };
 
+// Index of operand o at step index position kc = (kappa << rC) | c, split as
+// the thread's low 8 bits (fixed per thread, `lo`) and the bits above.
+__device__ __forceinline__ uint32_t wg_index(const OpDesc &o, uint32_t lo, uint32_t hi) {
+  return lo + (dpext(hi, o.mask >> 8) << __popc(o.mask & 255u));
+}
+
 template <bool SCALE>
 __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, const WgCtx &W) {
   const int nin = st.nin, rC = st.rC, nk = st.nk;
   const uint32_t t = threadIdx.x;
   const char *gptr[kMaxIn];
+  uint32_t lo[kMaxIn];
   int sh = 0, esum = 0;
 #pragma unroll
   for (int i = 0; i < kMaxIn; ++i) {
     gptr[i] = nullptr;
+    lo[i] = 0;
     if (i >= nin) continue;
     const OpDesc &o = st.in[i];
+    lo[i] = dpext(t & 255u, o.mask & 255u);
     if (o.loc == LOC_SCRATCH) {
       gptr[i] = W.scratch + o.off;
     } else if (o.loc == LOC_GLOBAL || o.loc == LOC_LEAF) {
@@ -227,7 +257,7 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
       gptr[i] = (const char *)o.base + inst_off(o, b, sl, s) * es;
     }
     if (SCALE) {
-      if (o.loc == LOC_LDS || o.loc == LOC_SCRATCH) {
+      if ((o.loc == LOC_LDS || o.loc == LOC_SCRATCH) && o.slot >= 0) {
         const int e = exp_of_bits(W.sM[o.slot]);
         sh += e;
         esum += W.sE[o.slot] + e;
@@ -239,13 +269,15 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
       }
     }
   }
-  auto point = [&](uint32_t c, uint32_t kap) -> double2 {
+  // product of the operands at the point whose step index has low 8 bits
+  // equal to this thread's and bits `hi` above them
+  auto point = [&](uint32_t hi) -> double2 {
     double2 prod = make_double2(1.0, 0.0);
 #pragma unroll
     for (int i = 0; i < kMaxIn; ++i) {
       if (i >= nin) continue;
       const OpDesc &o = st.in[i];
-      const uint32_t idx = (uint32_t)cpart(o, c) + o.tab[272 + kap];
+      const uint32_t idx = wg_index(o, lo[i], hi);
       double2 v;
       if (o.loc == LOC_LDS)
         v = W.lds[o.off / 16 + idx];
@@ -272,10 +304,12 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
   uint32_t mx = 0;
   if (rC >= 8) {
     const uint32_t nkap = 1u << nk;
-    for (uint32_t c = t; c < nC; c += 256) {
+    const uint32_t rows = nC >> 8;
+    for (uint32_t j = 0; j < rows; ++j) {
+      const uint32_t c = (j << 8) | t;
       double2 acc = make_double2(0.0, 0.0);
       for (uint32_t k = 0; k < nkap; ++k) {
-        const double2 p = point(c, k);
+        const double2 p = point((k << (rC - 8)) | j);
         acc.x += p.x;
         acc.y += p.y;
       }
@@ -296,7 +330,7 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
     if (kl < (1u << kb)) {
       const uint32_t nkh = 1u << (nk - kb);
       for (uint32_t kh = 0; kh < nkh; ++kh) {
-        const double2 p = point(c, (kh << kb) | kl);
+        const double2 p = point(kh);
         acc.x += p.x;
         acc.y += p.y;
       }
@@ -337,18 +371,49 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
   __syncthreads();
 }
 
+// Copies the gate factors of a program into LDS for instance (b, s).  Wave w
+// takes factors w, w+4, ...; eight loads are in flight before any store.
+__device__ void stage_leaves(const LeafStage *ls, uint32_t n, uint32_t b, uint32_t s, double2 *lds) {
+  constexpr int G = 8;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (uint32_t j0 = w * G; j0 < n; j0 += 4 * G) {
+    double2 v[G];
+    uint32_t dst[G];
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      dst[r] = ~0u;
+      const uint32_t j = j0 + r;
+      if (j < n) {
+        const LeafStage &L = ls[j];
+        const double2 *src = L.base + b * L.bstride + (uint64_t)dpext(s, L.selmask) * L.vsize;
+        if (lane < L.count) {
+          v[r] = src[lane];
+          dst[r] = L.lds_off + lane;
+        }
+        for (uint32_t i = lane + 64; i < L.count; i += 64) lds[L.lds_off + i] = src[i];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < G; ++r)
+      if (dst[r] != ~0u) lds[dst[r]] = v[r];
+  }
+}
+
 // Persistent workgroups walk the items of one launch group.  The items of
 // program j are its instances, (bitstring, slice) or fewer when the program's
 // root does not depend on them; item -> (program, instance) by scanning the
 // group's program list.  Items never wait on each other.
 template <bool SCALE>
-__global__ __launch_bounds__(256) void wg_programs(const PStep *steps, const ProgDesc *progs,
-                                                   const int *plist, uint32_t nprog,
+__global__ __launch_bounds__(256) void wg_programs(const PStep *__restrict__ steps,
+                                                   const ProgDesc *__restrict__ progs,
+                                                   const LeafStage *__restrict__ stages,
+                                                   const int *__restrict__ plist, uint32_t nprog,
                                                    uint32_t nbits, uint32_t total, uint64_t s_lo,
                                                    uint32_t ns_wave, char *scratch,
                                                    uint64_t scratch_per_wg, uint32_t lds_bytes,
                                                    int max_slots) {
-  extern __shared__ __align__(16) char smem[];
+  char *smem = wg_smem;
   WgCtx W;
   W.lds = (double2 *)smem;
   W.red = (double2 *)(smem + lds_bytes);
@@ -369,6 +434,11 @@ __global__ __launch_bounds__(256) void wg_programs(const PStep *steps, const Pro
     const uint32_t b = q / ns;
     const uint32_t sl = q - b * ns;
     const uint32_t s = (uint32_t)(s_lo + sl);
+    if (P.nstage) {
+      __syncthreads();  // the previous item's steps are done with the LDS
+      stage_leaves(stages + P.stage0, P.nstage, b, s, W.lds);
+      __syncthreads();
+    }
     for (uint32_t k = 0; k < P.nsteps; ++k) wg_step<SCALE>(steps[P.step0 + k], b, sl, s, W);
   }
 }
@@ -530,6 +600,114 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
   }
 }
 
+// Streaming steps whose varying operands are re-read many times per row.
+// For a row of 256 consecutive output elements, operand v is touched at
+// base_v(row) + pext(c & 255, mask) + (pext(kappa, kmask) << pc): 2^nkv runs
+// of 2^nlo contiguous elements (pext keeps the summed bits on top and the
+// low output bits at the bottom of the operand index).  The block stages
+// those runs in LDS once per row and sums over kappa from LDS, so each
+// operand element is fetched once per row instead of once per use.
+template <bool SCALE, int NK, int NV, int NF>
+__global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, uint32_t ns,
+                                                  uint64_t s_lo, uint32_t jspan) {
+  constexpr uint32_t NKAP = 1u << NK;
+  extern __shared__ __align__(16) char stage[];
+  __shared__ uint32_t s_mid[NV][16];
+  __shared__ uint32_t s_kap[NV][NKAP];
+  __shared__ double2 s_coef[NKAP];
+  __shared__ uint32_t red4[4];
+  const uint32_t t = threadIdx.x;
+  if (t < NV * 16) s_mid[t >> 4][t & 15] = d.in[t >> 4].tab[256 + (t & 15)];
+  if (t < NV * NKAP) {
+    const OpDesc &in = d.in[t / NKAP];
+    s_kap[t / NKAP][t % NKAP] = (in.tab[272 + t % NKAP] >> in.pc) << in.nlo;
+  }
+  uint32_t lo[NV], soff[NV];
+  uint32_t bytes = 0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    lo[v] = d.in[v].tab[t];
+    soff[v] = bytes;
+    bytes += (1u << (d.in[v].nkv + d.in[v].nlo)) * (v < NF ? 8u : 16u);
+  }
+  const uint64_t Q = (uint64_t)nb * ns;
+  const uint32_t rows = (1u << d.rC) >> 8;
+  const uint32_t units = rows / jspan;
+  for (uint64_t q = blockIdx.y; q < Q; q += gridDim.y) {
+    InstanceSetup I;
+    setup_instance<SCALE>(d, ns, q, s_lo, I);
+    __syncthreads();
+    if (t < NKAP) {
+      double2 c = make_double2(1.0, 0.0);
+#pragma unroll
+      for (int i = NV; i < kMaxIn; ++i)
+        if (i < d.nin) c = cmul(c, load_g(d.in[i].base, d.in[i].f64, I.off[i] + d.in[i].tab[272 + t]));
+      s_coef[t] = c;
+    }
+    char *op = (char *)d.out.base + I.obase * (d.out.f64 ? 16u : 8u);
+    const uint32_t of = d.out.f64;
+    const int sh = I.sh;
+    uint32_t wmax = 0;
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+#pragma unroll 1
+      for (uint32_t jj = 0; jj < jspan; ++jj) {
+        const uint32_t row = u * jspan + jj;
+        __syncthreads();  // the previous row's readers are done
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const OpDesc &in = d.in[v];
+          const uint64_t rb = I.off[v] + s_mid[v][row & 15u] +
+                              ((uint64_t)dpext(row >> 4, in.hi_mask) << in.hi_shift);
+          const uint32_t nlo = in.nlo, pc = in.pc;
+          const uint32_t n = 1u << (in.nkv + nlo);
+          const uint32_t lmask = (1u << nlo) - 1u;
+          for (uint32_t e = t; e < n; e += 256) {
+            const uint64_t g = rb + ((uint64_t)(e >> nlo) << pc) + (e & lmask);
+            if (v < NF)
+              ((float2 *)(stage + soff[v]))[e] = ((const float2 *)in.base)[g];
+            else
+              ((double2 *)(stage + soff[v]))[e] = ((const double2 *)in.base)[g];
+          }
+        }
+        __syncthreads();
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (uint32_t k = 0; k < NKAP; ++k) {
+          double2 prod = s_coef[k];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const uint32_t idx = s_kap[v][k] + lo[v];
+            double2 x;
+            if (v < NF) {
+              const float2 f = ((const float2 *)(stage + soff[v]))[idx];
+              x = make_double2((double)f.x, (double)f.y);
+            } else {
+              x = ((const double2 *)(stage + soff[v]))[idx];
+            }
+            prod = cmul(prod, x);
+          }
+          acc.x += prod.x;
+          acc.y += prod.y;
+        }
+        if (SCALE) {
+          acc.x = ldexp(acc.x, -sh);
+          acc.y = ldexp(acc.y, -sh);
+          wmax = max(wmax, max_bits(acc, of));
+        }
+        store_g(op, of, ((uint64_t)row << 8) | t, acc);
+      }
+    }
+    if (SCALE) {
+      const uint32_t m = block_max(wmax, red4);
+      if (t == 0) {
+        raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots + (blockIdx.x % kMaxSlots), m);
+        if (blockIdx.x == 0) d.out.E[I.qo] = I.esum;
+      }
+    }
+    __syncthreads();  // s_coef and the stage are rewritten for the next instance
+  }
+}
+
 // Other grid-wide steps: one flat index over (instance, output element).
 template <bool SCALE>
 __global__ __launch_bounds__(256) void step_small(const PStep d, uint32_t nb, uint32_t ns,
@@ -678,6 +856,8 @@ static int upload(T **dst, const std::vector<T> &src, const char *what) {
 
 using namespace qtn;
 
+static uint32_t tiled_lds_bytes(const PStep &d);
+
 extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t bytes,
                                        uint64_t S) {
   set_error("");
@@ -803,7 +983,10 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     o.slot = X.slot[tid];
     const uint64_t size = 1ull << T.rank();
     if (T.leaf) {
-      o.loc = LOC_LEAF;
+      // staged factors are read from the program's LDS; the source fields
+      // stay for the staging list
+      o.loc = X.loc[tid] == LOC_LDS ? LOC_LDS : LOC_LEAF;
+      o.slot = -1;
       o.f64 = 1;
       o.base = (const double *)D->leafbuf + 2 * D->leaf_elem_off[tid];
       o.vsize = size;
@@ -851,24 +1034,49 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
       d.in[j].hi_mask = it.hi_mask;
       d.in[j].hi_shift = it.hi_shift;
       d.in[j].cvary = (S_.mask[i] & cbits) ? 1u : 0u;
+      d.in[j].pc = (uint32_t)__builtin_popcount(S_.mask[i] & cbits);
+      d.in[j].nlo = (uint32_t)__builtin_popcount(S_.mask[i] & cbits & 255u);
+      d.in[j].nkv = (uint32_t)__builtin_popcount(S_.rC >= 32 ? 0u : (S_.mask[i] >> S_.rC));
+      d.in[j].mask = S_.mask[i];
       d.nvary += (int)d.in[j].cvary;
     }
     describe(S_.out, d.out);
+    d.tiled_lds = tiled_lds_bytes(d);
   }
   // program steps, contiguous per program
   std::vector<PStep> packed;
   std::vector<ProgDesc> progs;
+  std::vector<LeafStage> stages;
   for (const Program &pr : X.programs) {
     ProgDesc pd;
+    std::memset(&pd, 0, sizeof(pd));
     pd.step0 = (uint32_t)packed.size();
     pd.nsteps = (uint32_t)pr.steps.size();
     pd.bdep = pr.bdep;
     pd.sdep = pr.sdep;
+    pd.stage0 = (uint32_t)stages.size();
+    pd.nstage = (uint32_t)pr.staged.size();
+    for (int tid : pr.staged) {
+      const Tensor &T = sch.tensors[tid];
+      OpDesc o;
+      describe(tid, o);
+      LeafStage ls;
+      std::memset(&ls, 0, sizeof(ls));
+      ls.base = (const double2 *)o.base;
+      ls.bstride = o.bstride;
+      ls.vsize = o.vsize;
+      ls.selmask = o.selmask;
+      ls.count = 1u << T.rank();
+      ls.lds_off = (uint32_t)(X.off[tid] / 16);
+      stages.push_back(ls);
+    }
     for (int st : pr.steps) packed.push_back(D->steps[st]);
     progs.push_back(pd);
   }
+  if (stages.empty()) stages.emplace_back();
   if (int rc = upload(&D->stepbuf, packed, "hipMalloc(program steps)")) return rc;
   if (int rc = upload(&D->progbuf, progs, "hipMalloc(programs)")) return rc;
+  if (int rc = upload(&D->stagebuf, stages, "hipMalloc(staged factors)")) return rc;
   std::vector<int> pl;
   D->group_plist_off.clear();
   for (const LaunchGroup &g : X.launches) {
@@ -879,6 +1087,29 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   return QTN_OK;
 }
 
+// LDS bytes of step_tiled for this step, or 0 when staging does not pay:
+// the rows must be whole, every varying operand in global memory, the staged
+// runs at most a third of the direct loads and small enough for several
+// blocks per compute unit.
+static uint32_t tiled_lds_bytes(const PStep &d) {
+  static const bool enabled = [] {
+    const char *e = std::getenv("QTN_TILED");  // tuning switch: 0 keeps step_stream
+    return !(e && e[0] == '0');
+  }();
+  if (!enabled || d.rC < 8 || d.nk > 4 || d.nvary < 1 || d.nvary > 4) return 0;
+  uint64_t staged = 0, bytes = 0;
+  for (int v = 0; v < d.nvary; ++v) {
+    const OpDesc &in = d.in[v];
+    if (in.loc != LOC_GLOBAL && in.loc != LOC_LEAF) return 0;
+    const uint64_t n = 1ull << (in.nkv + in.nlo);
+    staged += n;
+    bytes += n * (v < d.nf32 ? 8u : 16u);
+  }
+  const uint64_t direct = (uint64_t)d.nvary * 256u << d.nk;
+  if (3 * staged > direct || bytes > 48 * 1024) return 0;
+  return (uint32_t)bytes;
+}
+
 template <bool SCALE, int NK, int NV>
 static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint32_t nb, uint32_t ns,
                              uint64_t s_lo, uint32_t jspan) {
@@ -887,8 +1118,14 @@ static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint
 #define QTN_NF(F)                                                                                  \
   case F:                                                                                          \
     if constexpr (F <= NV)                                                                         \
-      hipLaunchKernelGGL((step_stream<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256), 0,      \
-                         stream, d, nb, ns, s_lo, jspan);                                          \
+    {                                                                                              \
+      if (d.tiled_lds)                                                                             \
+        hipLaunchKernelGGL((step_tiled<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256),        \
+                           d.tiled_lds, stream, d, nb, ns, s_lo, jspan);                           \
+      else                                                                                         \
+        hipLaunchKernelGGL((step_stream<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256), 0,    \
+                           stream, d, nb, ns, s_lo, jspan);                                        \
+    }                                                                                              \
     break;
     QTN_NF(0) QTN_NF(1) QTN_NF(2) QTN_NF(3) QTN_NF(4)
 #undef QTN_NF
@@ -949,6 +1186,7 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
         const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
         hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), D->lds_total,
                            stream, (const PStep *)D->stepbuf, (const ProgDesc *)D->progbuf,
+                           (const LeafStage *)D->stagebuf,
                            (const int *)(D->plistbuf + D->group_plist_off[g]),
                            (uint32_t)G.programs.size(), (uint32_t)B, (uint32_t)total, s_lo,
                            (uint32_t)cnt, D->ws + D->L.scratch_off, scratch_stride,
