@@ -340,6 +340,8 @@ extern "C" int qtn_plan_workspace_bytes(const qtn_plan_t *P, uint64_t S, uint64_
   Schedule copy = P->sched;
   try {
     Layout L = layout(copy, P->exec[mode], P->net.B, S, wg_slots_for(P, mode, S));
+    // the stream assignment of the launches checks itself as well
+    (void)launch_graph(copy, P->exec[mode], L, P->net.B, S, P->precision != QTN_FP64, 4);
     *bytes = L.total_bytes;
   } catch (const std::exception &e) {
     return fail(QTN_ESTATE, e.what());

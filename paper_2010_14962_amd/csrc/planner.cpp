@@ -7,6 +7,7 @@
 #include <cmath>
 #include <functional>
 #include <map>
+#include <set>
 #include <numeric>
 #include <stdexcept>
 
@@ -853,6 +854,115 @@ Layout layout(Schedule &s, const ExecPlan &x, uint64_t B, uint64_t S, uint64_t w
   L.wg_slots = wg_slots;
   L.total_bytes = align256(L.scratch_off + wg_slots * align256(x.scratch_per_wg));
   return L;
+}
+
+LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, uint64_t B,
+                         uint64_t S, bool scaled, int max_streams) {
+  struct Range {
+    uint64_t lo, hi;
+    bool write;
+  };
+  const size_t nl = x.launches.size();
+  const size_t U = nl + 2;
+  std::vector<std::vector<Range>> rng(U);
+  auto global = [&](int t) { return !s.tensors[t].leaf && x.loc[t] == LOC_GLOBAL; };
+  auto data = [&](int t, bool w, std::vector<Range> &r) {
+    const Tensor &T = s.tensors[t];
+    const uint64_t n = align256(instances(T, B, S) * ((uint64_t)1 << T.rank()) * (uint64_t)elem_bytes(T));
+    r.push_back({T.data_off, T.data_off + n, w});
+    if (scaled) {
+      const uint64_t e = align256(instances(T, B, S) * 4 * (1 + kMaxSlots));
+      r.push_back({T.exp_off, T.exp_off + e, w});
+    }
+  };
+  if (scaled && L.exp_bytes) rng[0].push_back({L.data_bytes, L.data_bytes + L.exp_bytes, true});
+  for (size_t g = 0; g < nl; ++g) {
+    const LaunchGroup &G = x.launches[g];
+    std::vector<int> sts;
+    if (G.kind == 1) {
+      sts.push_back(G.step);
+    } else {
+      for (int p : G.programs)
+        for (int st : x.programs[p].steps) sts.push_back(st);
+      if (x.scratch_per_wg) rng[g + 1].push_back({L.scratch_off, L.total_bytes, true});
+    }
+    std::set<int> made;
+    for (int st : sts) made.insert(s.steps[st].out);
+    for (int st : sts) {
+      for (int i : s.steps[st].in)
+        if (global(i) && !made.count(i)) data(i, false, rng[g + 1]);
+      if (global(s.steps[st].out)) data(s.steps[st].out, true, rng[g + 1]);
+    }
+  }
+  data(s.result, false, rng[nl + 1]);
+  rng[nl + 1].push_back({L.partial_off, L.partial_off + B * 32, true});
+
+  auto conflict = [&](size_t a, size_t b) {
+    for (const Range &p : rng[a])
+      for (const Range &q : rng[b])
+        if ((p.write || q.write) && p.lo < q.hi && q.lo < p.hi) return true;
+    return false;
+  };
+  LaunchGraph G;
+  G.deps.assign(U, {});
+  std::vector<std::vector<char>> anc(U, std::vector<char>(U, 0));  // anc[v][u]: u before v
+  for (size_t v = 0; v < U; ++v) {
+    std::vector<int> direct;
+    for (size_t u = v; u-- > 0;)
+      if (conflict(u, v)) direct.push_back((int)u);
+    // transitive reduction: drop u when a later kept dependency already follows it
+    for (int u : direct) {  // descending
+      bool implied = false;
+      for (int w : G.deps[v])
+        if (anc[w][u]) {
+          implied = true;
+          break;
+        }
+      if (!implied) G.deps[v].push_back(u);
+    }
+    for (int u : G.deps[v]) {
+      anc[v][u] = 1;
+      for (size_t a = 0; a < U; ++a)
+        if (anc[u][a]) anc[v][a] = 1;
+    }
+  }
+  // streams: follow the latest dependency's stream when it ends there, else
+  // take the stream whose last unit is oldest
+  const int ns = std::max(1, max_streams);
+  G.stream.assign(U, 0);
+  G.record.assign(U, 0);
+  std::vector<int> tail(ns, -1);
+  for (size_t v = 0; v < U; ++v) {
+    int pick = -1;
+    for (int u : G.deps[v])  // latest first
+      if (tail[G.stream[u]] == u) {
+        pick = G.stream[u];
+        break;
+      }
+    if (pick < 0) {
+      // a stream whose last unit is already an ancestor adds no ordering
+      for (int k = 0; k < ns && pick < 0; ++k)
+        if (tail[k] < 0 || anc[v][tail[k]]) pick = k;
+    }
+    if (pick < 0) {
+      pick = 0;
+      for (int k = 1; k < ns; ++k)
+        if (tail[k] < tail[pick]) pick = k;
+    }
+    G.stream[v] = pick;
+    tail[pick] = (int)v;
+    for (int u : G.deps[v])
+      if (G.stream[u] != pick) G.record[u] = 1;
+    G.nstreams = std::max(G.nstreams, pick + 1);
+  }
+  // self-check: units left unordered never touch conflicting bytes
+  for (size_t v = 0; v < U; ++v)
+    for (size_t u = 0; u < v; ++u) {
+      bool ordered = anc[v][u] != 0;
+      if (!ordered && G.stream[u] == G.stream[v]) ordered = true;  // same stream: FIFO
+      if (!ordered && conflict(u, v)) throw std::runtime_error("launch graph misses a dependency");
+    }
+  return G;
 }
 
 Costs schedule_costs(const Schedule &s, uint64_t B, uint64_t S) {

@@ -204,6 +204,20 @@ inline int elem_bytes(const Tensor &t) { return t.f64 ? 16 : 8; }
 // per-workgroup scratch for `wg_slots` workgroups, partial sums.
 Layout layout(Schedule &s, const ExecPlan &x, uint64_t B, uint64_t S, uint64_t wg_slots);
 
+// Launch units of one wave: 0 clears the exponent region, 1..n are the
+// launch groups of the execution plan, n+1 is the slice sum.  A unit depends
+// on every earlier unit whose workspace bytes it reads or writes while the
+// other writes them (or reads what it writes); units that do not depend on
+// each other may run on different streams.
+struct LaunchGraph {
+  std::vector<std::vector<int>> deps;  // direct predecessors, transitively reduced
+  std::vector<int> stream;             // stream of each unit (0 = the caller's)
+  std::vector<char> record;            // another stream waits for this unit
+  int nstreams = 1;
+};
+LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, uint64_t B,
+                         uint64_t S, bool scaled, int max_streams);
+
 struct Costs {
   double flops_per_slice = 0;    // all bitstrings
   double bytes_per_slice = 0;

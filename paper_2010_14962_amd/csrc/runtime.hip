@@ -24,27 +24,25 @@ namespace qtn {
 // ---------------------------------------------------------------------------
 // Descriptors
 // ---------------------------------------------------------------------------
+// Operand of a step.  Every index map follows from `mask`, the operand's bits
+// over the step index kappa:c (kappa above the rC output bits): the operand
+// index of step index x is pext(x, mask).
 struct OpDesc {
   const void *base;       // GLOBAL: workspace tensor; LEAF: leaf block
   uint64_t bstride;       // elements between bitstrings
   uint64_t sstride;       // elements between slice-local instances
-  uint64_t vsize;         // leaves: elements per slice variant
-  const uint32_t *tab;    // lo[256] | mid[16] | kap[2^nk]
   int *E;                 // GLOBAL scaled tensors: exponent per instance
-  uint32_t *M;            // GLOBAL scaled tensors: max |component| exponent bits
+  uint32_t *M;            // GLOBAL scaled tensors: kMaxSlots max-exponent words each
   uint32_t ebstride, esstride;
-  uint32_t selmask;       // leaves: slice bits that pick the variant
-  uint32_t hi_mask, hi_shift;
-  uint32_t loc;           // Loc
-  uint32_t f64;           // stored as complex128 (else complex64)
-  uint32_t off;           // LDS / scratch byte offset
-  int slot;               // LDS / scratch: exponent slot
-  uint32_t cvary;         // index depends on the output element
-  uint32_t pc;            // popcount of the output part of the mask
-  uint32_t nlo;           // popcount of its lowest 8 bits
-  uint32_t nkv;           // popcount of the kappa part of the mask
+  // the last 16 bytes are what a workgroup program step reads first
   uint32_t mask;          // operand bits over the step index kappa:c
+  uint32_t off;           // LDS / scratch byte offset
+  int16_t slot;           // LDS / scratch: exponent slot, -1 for none
+  uint8_t loc;            // Loc
+  uint8_t f64;            // stored as complex128 (else complex64)
+  uint32_t selmask;       // leaves: slice bits that pick the variant
 };
+static_assert(sizeof(OpDesc) == 64, "OpDesc layout");
 
 struct PStep {
   OpDesc in[kMaxIn];      // operands varying with the output element first
@@ -53,39 +51,48 @@ struct PStep {
   int nvary;              // in[0..nvary) vary with the output element
   int nf32;               // of those, in[0..nf32) are stored as complex64
   uint32_t tiled_lds;     // > 0: run as step_tiled with this much LDS
+  int pad[2];
 };
-
-struct ProgDesc {
-  uint32_t step0, nsteps;
-  uint32_t bdep, sdep;
-  uint32_t stage0, nstage;    // gate factors staged in LDS at program start
-};
+static_assert(sizeof(PStep) % 16 == 0, "PStep layout");
 
 // One gate factor a program stages in LDS: the variant of instance (b, s)
-// is base + b * bstride + pext(s, selmask) * vsize, count complex128 values.
+// is base + b * bstride + pext(s, selmask) * count, count complex128 values.
 struct LeafStage {
   const double2 *base;
-  uint64_t bstride, vsize;
+  uint64_t bstride;
   uint32_t selmask, count, lds_off, pad;
+};
+static_assert(sizeof(LeafStage) == 32, "LeafStage layout");
+
+// A program in device memory is one blob: its LeafStage records, then its
+// PStep descriptors.  A launch of workgroup programs names up to
+// kMaxGroupProgs of them in its arguments, so that a workgroup finds its
+// program without a memory round trip.
+constexpr int kMaxGroupProgs = 32;
+constexpr int kDescChunk = 8;          // program steps resident in LDS at a time
+struct GroupArgs {
+  uint32_t nprog;
+  uint32_t blob_off[kMaxGroupProgs];   // bytes from the blob base
+  uint32_t item_end[kMaxGroupProgs];   // cumulative item counts
+  uint16_t nsteps[kMaxGroupProgs];
+  uint16_t nstage[kMaxGroupProgs];
+  uint8_t bdep[kMaxGroupProgs];
+  uint8_t sdep[kMaxGroupProgs];
 };
 
 struct DeviceState {
   int device = -1;
   int mode = MODE_WIDE;
   void *leafbuf = nullptr;        // complex128 gate factors
-  uint32_t *tabbuf = nullptr;     // index tables
-  PStep *stepbuf = nullptr;       // program steps, contiguous per program
-  ProgDesc *progbuf = nullptr;
-  int *plistbuf = nullptr;        // program ids of every launch group
-  LeafStage *stagebuf = nullptr;  // staged gate factors of every program
+  char *blobbuf = nullptr;        // program blobs
+  std::vector<uint64_t> blob_off; // per program
   std::vector<uint64_t> leaf_elem_off;
-  std::vector<std::vector<uint64_t>> tab_off;
   std::vector<PStep> steps;       // one descriptor per schedule step (host copy)
-  std::vector<uint64_t> group_plist_off;
   char *ws = nullptr;
   uint64_t ws_bytes = 0;
   Layout L;
   uint32_t lds_bytes = 0, lds_total = 0;
+  uint32_t desc_bytes = 0;        // program descriptor region of the LDS
   int max_slots = 0;
   // optional per-launch timing of the streaming step kernel
   bool timing = false;
@@ -96,6 +103,15 @@ struct DeviceState {
   uint64_t t_launches = 0, t_failed = 0;
   int t_last_error = 0;
   std::vector<double> step_bytes, step_flops;  // per instance of each step
+  // independent launch units run on side streams (default priority),
+  // ordered by events after their dependencies
+  LaunchGraph lg;
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {nullptr, nullptr, nullptr};
+  std::vector<hipEvent_t> unit_ev;
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kSide] = {nullptr, nullptr, nullptr};
+  int max_streams = 1 + kSide;
   // captured launch sequence of one slice range, replayed while it matches
   bool use_graphs = true;
   hipStream_t gstream = nullptr;
@@ -117,9 +133,14 @@ void device_state_free(DeviceState *d) {
   drop_graph(d);
   if (d->gdep) (void)hipEventDestroy(d->gdep);
   if (d->gstream) (void)hipStreamDestroy(d->gstream);
+  for (auto e : d->unit_ev) (void)hipEventDestroy(e);
+  if (d->fork_ev) (void)hipEventDestroy(d->fork_ev);
+  for (int k = 0; k < DeviceState::kSide; ++k) {
+    if (d->join_ev[k]) (void)hipEventDestroy(d->join_ev[k]);
+    if (d->side[k]) (void)hipStreamDestroy(d->side[k]);
+  }
   for (auto e : d->ev) (void)hipEventDestroy(e);
-  for (void *p : {(void *)d->leafbuf, (void *)d->tabbuf, (void *)d->stepbuf,
-                  (void *)d->progbuf, (void *)d->plistbuf, (void *)d->stagebuf})
+  for (void *p : {(void *)d->leafbuf, (void *)d->blobbuf})
     if (p) (void)hipFree(p);
   delete d;
 }
@@ -180,7 +201,8 @@ __device__ __forceinline__ uint32_t wave_max(uint32_t m) {
 }
 
 // Block-wide max over 256 threads; every thread must call it.
-__device__ __forceinline__ uint32_t block_max(uint32_t m, uint32_t *red4) {
+template <typename P>
+__device__ __forceinline__ uint32_t block_max(uint32_t m, P red4) {
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -202,16 +224,23 @@ __device__ __forceinline__ uint32_t slots_max(const uint32_t *M) {
   return m;
 }
 
-__device__ __forceinline__ uint64_t inst_off(const OpDesc &o, uint32_t b, uint32_t sl, uint32_t s) {
+// Offset of the operand's block for instance (bitstring b, slice-local sl,
+// slice s); a leaf's variant holds 2^popcount(mask) values.
+template <typename D>
+__device__ __forceinline__ uint64_t inst_off(const D &o, uint32_t b, uint32_t sl, uint32_t s) {
   uint64_t r = (uint64_t)b * o.bstride + (uint64_t)sl * o.sstride;
-  if (o.selmask) r += (uint64_t)dpext(s, o.selmask) * o.vsize;
+  if (o.selmask) r += (uint64_t)dpext(s, o.selmask) << __popc(o.mask);
   return r;
 }
 
-__device__ __forceinline__ uint64_t cpart(const OpDesc &o, uint32_t c) {
-  uint64_t r = o.tab[c & 255u] + o.tab[256 + ((c >> 8) & 15u)];
-  if (o.hi_mask) r += (uint64_t)dpext(c >> 12, o.hi_mask) << o.hi_shift;
-  return r;
+__device__ __forceinline__ uint32_t out_bits(int rC) { return rC >= 32 ? ~0u : ((1u << rC) - 1u); }
+
+// Operand index contributed by output element c and by summed value kappa.
+__device__ __forceinline__ uint32_t cpart(const OpDesc &o, uint32_t c, int rC) {
+  return dpext(c, o.mask & out_bits(rC));
+}
+__device__ __forceinline__ uint32_t kpart(const OpDesc &o, uint32_t kap, int rC) {
+  return rC >= 32 ? 0u : (dpext(kap, o.mask >> rC) << __popc(o.mask & out_bits(rC)));
 }
 
 // ---------------------------------------------------------------------------
@@ -221,47 +250,92 @@ __device__ __forceinline__ uint64_t cpart(const OpDesc &o, uint32_t c) {
 // slots | 4 reduction words.
 extern __shared__ __align__(16) char wg_smem[];
 
+// LDS-qualified pointee types, so that every access compiles to an LDS
+// instruction rather than a generic (flat) one.
+#define QTN_LDS __attribute__((address_space(3)))
+
+// complex128 values in LDS as (re, im) pairs of doubles
+__device__ __forceinline__ double2 lds_ld(const QTN_LDS double *p, uint32_t i) {
+  return make_double2(p[2 * i], p[2 * i + 1]);
+}
+__device__ __forceinline__ void lds_st(QTN_LDS double *p, uint32_t i, double2 v) {
+  p[2 * i] = v.x;
+  p[2 * i + 1] = v.y;
+}
+
 struct WgCtx {
-  double2 *lds;           // program tensors (complex128)
-  double2 *red;           // 256 partial sums
-  int *sE;                // exponent slots
-  uint32_t *sM;
-  uint32_t *red4;
+  QTN_LDS double *lds;    // program tensors (complex128)
+  QTN_LDS double *red;    // 256 partial sums (complex128)
+  QTN_LDS int *sE;        // exponent slots
+  QTN_LDS uint32_t *sM;
+  QTN_LDS uint32_t *red4;
   char *scratch;          // this workgroup's global scratch
 };
 
-// Index of operand o at step index position kc = (kappa << rC) | c, split as
-// the thread's low 8 bits (fixed per thread, `lo`) and the bits above.
-__device__ __forceinline__ uint32_t wg_index(const OpDesc &o, uint32_t lo, uint32_t hi) {
-  return lo + (dpext(hi, o.mask >> 8) << __popc(o.mask & 255u));
-}
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// One step of a workgroup program.  Complex128 tensors in LDS are not
+// rescaled: they carry their power-of-two exponent in sE[slot] and FP64 has
+// range to spare.  Outputs stored in global memory or scratch keep the
+// rescaled form of the grid steps (values times 2^-sh, maximum tracked).
 template <bool SCALE>
-__device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, const WgCtx &W) {
-  const int nin = st.nin, rC = st.rC, nk = st.nk;
+__device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32_t s, const WgCtx &W) {
   const uint32_t t = threadIdx.x;
+  const int nin = (int)uni((uint32_t)st.nin), rC = (int)uni((uint32_t)st.rC), nk = (int)uni((uint32_t)st.nk);
+  // operand keys, read in one batch
+  uint32_t mk[kMaxIn], ok[kMaxIn], mt[kMaxIn];
+#pragma unroll
+  for (int i = 0; i < kMaxIn; ++i) {
+    mk[i] = st.in[i].mask;
+    ok[i] = st.in[i].off;
+    mt[i] = *(const QTN_LDS uint32_t *)&st.in[i].slot;   // slot | loc << 16 | f64 << 24
+  }
+  const uint32_t omt = *(const QTN_LDS uint32_t *)&st.out.slot;
+  const uint32_t ooff = uni(st.out.off);
+  bool all_lds = true;
+  uint32_t lo[kMaxIn], loff[kMaxIn], hm[kMaxIn], hs[kMaxIn];
+#pragma unroll
+  for (int i = 0; i < kMaxIn; ++i) {
+    const bool used = i < nin;
+    const uint32_t m = used ? uni(mk[i]) : 0u;
+    mk[i] = m;
+    mt[i] = uni(mt[i]);
+    lo[i] = dpext(t & 255u, m & 255u);
+    hm[i] = m >> 8;
+    hs[i] = __popc(m & 255u);
+    loff[i] = used ? uni(ok[i]) / 16 : 0u;
+    if (used && ((mt[i] >> 16) & 255u) != LOC_LDS) all_lds = false;
+  }
+  const bool wide_idx = rC + nk > 8;   // else every step index fits in the low 8 bits
+  // operands outside the LDS
   const char *gptr[kMaxIn];
-  uint32_t lo[kMaxIn];
+  uint32_t gf64[kMaxIn];
   int sh = 0, esum = 0;
 #pragma unroll
   for (int i = 0; i < kMaxIn; ++i) {
     gptr[i] = nullptr;
-    lo[i] = 0;
+    gf64[i] = 1;
     if (i >= nin) continue;
-    const OpDesc &o = st.in[i];
-    lo[i] = dpext(t & 255u, o.mask & 255u);
-    if (o.loc == LOC_SCRATCH) {
-      gptr[i] = W.scratch + o.off;
-    } else if (o.loc == LOC_GLOBAL || o.loc == LOC_LEAF) {
-      const uint64_t es = (o.loc == LOC_LEAF || o.f64) ? 16 : 8;
+    const uint32_t loc = (mt[i] >> 16) & 255u;
+    const int slot = (int16_t)(mt[i] & 0xffffu);
+    if (loc == LOC_SCRATCH) {
+      gptr[i] = W.scratch + uni(ok[i]);
+      gf64[i] = mt[i] >> 24;
+    } else if (loc == LOC_GLOBAL || loc == LOC_LEAF) {
+      const QTN_LDS OpDesc &o = st.in[i];
+      const uint64_t es = (loc == LOC_LEAF || (mt[i] >> 24)) ? 16 : 8;
       gptr[i] = (const char *)o.base + inst_off(o, b, sl, s) * es;
+      gf64[i] = loc == LOC_LEAF ? 1u : (mt[i] >> 24);
     }
     if (SCALE) {
-      if ((o.loc == LOC_LDS || o.loc == LOC_SCRATCH) && o.slot >= 0) {
-        const int e = exp_of_bits(W.sM[o.slot]);
+      if (loc == LOC_LDS && slot >= 0) {
+        esum += W.sE[slot];
+      } else if (loc == LOC_SCRATCH && slot >= 0) {
+        const int e = exp_of_bits(W.sM[slot]);
         sh += e;
-        esum += W.sE[o.slot] + e;
-      } else if (o.loc == LOC_GLOBAL) {
+        esum += W.sE[slot] + e;
+      } else if (loc == LOC_GLOBAL) {
+        const QTN_LDS OpDesc &o = st.in[i];
         const uint32_t qi = b * o.ebstride + sl * o.esstride;
         const int e = exp_of_bits(slots_max(o.M + (uint64_t)qi * kMaxSlots));
         sh += e;
@@ -269,36 +343,41 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
       }
     }
   }
-  // product of the operands at the point whose step index has low 8 bits
-  // equal to this thread's and bits `hi` above them
+  // product of the operands at the step index whose low 8 bits are this
+  // thread's and whose bits above are `hi`
   auto point = [&](uint32_t hi) -> double2 {
-    double2 prod = make_double2(1.0, 0.0);
+    double2 v[kMaxIn];
 #pragma unroll
     for (int i = 0; i < kMaxIn; ++i) {
-      if (i >= nin) continue;
-      const OpDesc &o = st.in[i];
-      const uint32_t idx = wg_index(o, lo[i], hi);
-      double2 v;
-      if (o.loc == LOC_LDS)
-        v = W.lds[o.off / 16 + idx];
+      const uint32_t idx = lo[i] + (wide_idx ? (dpext(hi, hm[i]) << hs[i]) : 0u);
+      if (all_lds || ((mt[i] >> 16) & 255u) == LOC_LDS || i >= nin)
+        v[i] = lds_ld(W.lds, loff[i] + idx);
       else
-        v = load_g(gptr[i], o.loc == LOC_LEAF ? 1u : o.f64, idx);
-      prod = (i == 0) ? v : cmul(prod, v);
+        v[i] = load_g(gptr[i], gf64[i], idx);
     }
+    double2 prod = v[0];
+#pragma unroll
+    for (int i = 1; i < kMaxIn; ++i)
+      if (i < nin) prod = cmul(prod, v[i]);
     return prod;
   };
-  const OpDesc &out = st.out;
+  const uint32_t oloc = (omt >> 16) & 255u, of64 = oloc == LOC_LDS ? 1u : (omt >> 24);
+  const int oslot = (int16_t)(omt & 0xffffu);
+  const bool scale_out = SCALE && oloc != LOC_LDS;
+  const int shift = scale_out ? sh : 0;
+  if (!scale_out) esum -= sh;  // LDS outputs keep the unscaled products
   char *optr = nullptr;
-  if (out.loc == LOC_SCRATCH)
-    optr = W.scratch + out.off;
-  else if (out.loc == LOC_GLOBAL)
-    optr = (char *)out.base + ((uint64_t)b * out.bstride + (uint64_t)sl * out.sstride) * (out.f64 ? 16 : 8);
-  const uint32_t of64 = out.loc == LOC_LDS ? 1u : out.f64;
+  if (oloc == LOC_SCRATCH) {
+    optr = W.scratch + ooff;
+  } else if (oloc == LOC_GLOBAL) {
+    const QTN_LDS OpDesc &out = st.out;
+    optr = (char *)out.base + ((uint64_t)b * out.bstride + (uint64_t)sl * out.sstride) * (of64 ? 16 : 8);
+  }
   auto put = [&](uint32_t c, double2 v) {
-    if (out.loc == LOC_LDS)
-      W.lds[out.off / 16 + c] = v;
+    if (oloc == LOC_LDS)
+      lds_st(W.lds, ooff / 16 + c, v);
     else
-      store_g(optr, out.f64, c, v);
+      store_g(optr, of64, c, v);
   };
   const uint32_t nC = 1u << rC;
   uint32_t mx = 0;
@@ -313,9 +392,9 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
         acc.x += p.x;
         acc.y += p.y;
       }
-      if (SCALE) {
-        acc.x = ldexp(acc.x, -sh);
-        acc.y = ldexp(acc.y, -sh);
+      if (scale_out) {
+        acc.x = ldexp(acc.x, -shift);
+        acc.y = ldexp(acc.y, -shift);
         mx = max(mx, max_bits(acc, of64));
       }
       put(c, acc);
@@ -335,36 +414,39 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
         acc.y += p.y;
       }
     }
-    W.red[t] = acc;
-    __syncthreads();
-    for (uint32_t h = (1u << kb) >> 1; h >= 1; h >>= 1) {
-      if (kl < h) {
-        const double2 o = W.red[t + (h << rC)];
-        W.red[t].x += o.x;
-        W.red[t].y += o.y;
-      }
+    if (kb > 0) {
+      lds_st(W.red, t, acc);
       __syncthreads();
+      for (uint32_t h = (1u << kb) >> 1; h >= 1; h >>= 1) {
+        if (kl < h) {
+          const double2 o = lds_ld(W.red, t + (h << rC));
+          const double2 m = lds_ld(W.red, t);
+          lds_st(W.red, t, make_double2(m.x + o.x, m.y + o.y));
+        }
+        __syncthreads();
+      }
+      if (t < nC) acc = lds_ld(W.red, t);
     }
     if (t < nC) {
-      acc = W.red[t];
-      if (SCALE) {
-        acc.x = ldexp(acc.x, -sh);
-        acc.y = ldexp(acc.y, -sh);
+      if (scale_out) {
+        acc.x = ldexp(acc.x, -shift);
+        acc.y = ldexp(acc.y, -shift);
         mx = max_bits(acc, of64);
       }
       put(c, acc);
     }
   }
   if (SCALE) {
-    mx = block_max(mx, W.red4);
+    if (scale_out) mx = block_max(mx, W.red4);
     if (t == 0) {
-      if (out.loc == LOC_GLOBAL) {
+      if (oloc == LOC_GLOBAL) {
+        const QTN_LDS OpDesc &out = st.out;
         const uint32_t qo = b * out.ebstride + sl * out.esstride;
         out.E[qo] = esum;
         out.M[(uint64_t)qo * kMaxSlots] = mx;
       } else {
-        W.sE[out.slot] = esum;
-        W.sM[out.slot] = mx;
+        W.sE[oslot] = esum;
+        if (scale_out) W.sM[oslot] = mx;
       }
     }
   }
@@ -373,7 +455,8 @@ __device__ void wg_step(const PStep &st, uint32_t b, uint32_t sl, uint32_t s, co
 
 // Copies the gate factors of a program into LDS for instance (b, s).  Wave w
 // takes factors w, w+4, ...; eight loads are in flight before any store.
-__device__ void stage_leaves(const LeafStage *ls, uint32_t n, uint32_t b, uint32_t s, double2 *lds) {
+__device__ void stage_leaves(const QTN_LDS LeafStage *ls, uint32_t n, uint32_t b, uint32_t s,
+                             QTN_LDS double *lds) {
   constexpr int G = 8;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -385,61 +468,92 @@ __device__ void stage_leaves(const LeafStage *ls, uint32_t n, uint32_t b, uint32
       dst[r] = ~0u;
       const uint32_t j = j0 + r;
       if (j < n) {
-        const LeafStage &L = ls[j];
-        const double2 *src = L.base + b * L.bstride + (uint64_t)dpext(s, L.selmask) * L.vsize;
+        const QTN_LDS LeafStage &L = ls[j];
+        const double2 *src = L.base + b * L.bstride + (uint64_t)dpext(s, L.selmask) * L.count;
         if (lane < L.count) {
           v[r] = src[lane];
           dst[r] = L.lds_off + lane;
         }
-        for (uint32_t i = lane + 64; i < L.count; i += 64) lds[L.lds_off + i] = src[i];
+        for (uint32_t i = lane + 64; i < L.count; i += 64) lds_st(lds, L.lds_off + i, src[i]);
       }
     }
 #pragma unroll
     for (int r = 0; r < G; ++r)
-      if (dst[r] != ~0u) lds[dst[r]] = v[r];
+      if (dst[r] != ~0u) lds_st(lds, dst[r], v[r]);
   }
 }
 
-// Persistent workgroups walk the items of one launch group.  The items of
-// program j are its instances, (bitstring, slice) or fewer when the program's
-// root does not depend on them; item -> (program, instance) by scanning the
-// group's program list.  Items never wait on each other.
+// Copies n bytes (a multiple of 16) from global memory to LDS, four 16-byte
+// loads per thread in flight at a time.
+__device__ __forceinline__ void copy_to_lds(QTN_LDS char *dst, const char *__restrict__ src, uint32_t n) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  const uint32_t n16 = n >> 4;
+  for (uint32_t i0 = 0; i0 < n16; i0 += 4 * 256) {
+    u64x2 v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = i0 + r * 256 + threadIdx.x;
+      if (i < n16) v[r] = ((const u64x2 *)src)[i];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t i = i0 + r * 256 + threadIdx.x;
+      if (i < n16) ((QTN_LDS u64x2 *)dst)[i] = v[r];
+    }
+  }
+}
+
+// Persistent workgroups walk the items of one launch: the items of program
+// j are its instances, (bitstring, slice) or fewer when the program's root
+// does not depend on them.  Per item the workgroup copies the program's
+// staging records and first steps into LDS, stages the gate factors, then
+// runs the steps, kDescChunk descriptors at a time.  Items never wait on
+// each other.
 template <bool SCALE>
-__global__ __launch_bounds__(256) void wg_programs(const PStep *__restrict__ steps,
-                                                   const ProgDesc *__restrict__ progs,
-                                                   const LeafStage *__restrict__ stages,
-                                                   const int *__restrict__ plist, uint32_t nprog,
+__global__ __launch_bounds__(256) void wg_programs(const char *__restrict__ blobs, const GroupArgs ga,
                                                    uint32_t nbits, uint32_t total, uint64_t s_lo,
                                                    uint32_t ns_wave, char *scratch,
                                                    uint64_t scratch_per_wg, uint32_t lds_bytes,
-                                                   int max_slots) {
+                                                   int max_slots, uint32_t desc_off) {
   char *smem = wg_smem;
   WgCtx W;
-  W.lds = (double2 *)smem;
-  W.red = (double2 *)(smem + lds_bytes);
-  W.sE = (int *)(smem + lds_bytes + 256 * 16);
-  W.sM = (uint32_t *)(W.sE + max_slots);
+  QTN_LDS char *sm = (QTN_LDS char *)smem;
+  W.lds = (QTN_LDS double *)sm;
+  W.red = (QTN_LDS double *)(sm + lds_bytes);
+  W.sE = (QTN_LDS int *)(sm + lds_bytes + 256 * 16);
+  W.sM = (QTN_LDS uint32_t *)(W.sE + max_slots);
   W.red4 = W.sM + max_slots;
   W.scratch = scratch + (uint64_t)blockIdx.x * scratch_per_wg;
+  QTN_LDS char *desc = sm + desc_off;
+  (void)nbits;
   for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
-    uint32_t q = item, j = 0;
-    ProgDesc P = progs[plist[0]];
-    for (;;) {
-      const uint32_t n = (P.bdep ? nbits : 1u) * (P.sdep ? ns_wave : 1u);
-      if (q < n || j + 1 >= nprog) break;
-      q -= n;
-      P = progs[plist[++j]];
-    }
-    const uint32_t ns = P.sdep ? ns_wave : 1u;
+    uint32_t j = 0;
+    while (j + 1 < ga.nprog && item >= ga.item_end[j]) ++j;
+    const uint32_t q = item - (j ? ga.item_end[j - 1] : 0u);
+    const uint32_t ns = ga.sdep[j] ? ns_wave : 1u;
     const uint32_t b = q / ns;
     const uint32_t sl = q - b * ns;
     const uint32_t s = (uint32_t)(s_lo + sl);
-    if (P.nstage) {
-      __syncthreads();  // the previous item's steps are done with the LDS
-      stage_leaves(stages + P.stage0, P.nstage, b, s, W.lds);
+    const char *blob = blobs + ga.blob_off[j];
+    const uint32_t nst = ga.nsteps[j], nstg = ga.nstage[j];
+    const uint32_t lsb = nstg * (uint32_t)sizeof(LeafStage);
+    __syncthreads();  // the previous item is done with the LDS
+    copy_to_lds(desc, blob, lsb + min(nst, (uint32_t)kDescChunk) * (uint32_t)sizeof(PStep));
+    __syncthreads();
+    if (nstg) {
+      stage_leaves((const QTN_LDS LeafStage *)desc, nstg, b, s, W.lds);
       __syncthreads();
     }
-    for (uint32_t k = 0; k < P.nsteps; ++k) wg_step<SCALE>(steps[P.step0 + k], b, sl, s, W);
+    const QTN_LDS PStep *ps = (const QTN_LDS PStep *)(desc + lsb);
+    for (uint32_t k = 0; k < nst; ++k) {
+      if (k && k % kDescChunk == 0) {
+        // the previous step ended with a barrier
+        copy_to_lds(desc + lsb, blob + lsb + k * (uint32_t)sizeof(PStep),
+                    min(nst - k, (uint32_t)kDescChunk) * (uint32_t)sizeof(PStep));
+        __syncthreads();
+      }
+      wg_step<SCALE>(ps[k % kDescChunk], b, sl, s, W);
+    }
   }
 }
 
@@ -481,10 +595,10 @@ __device__ __forceinline__ void setup_instance(const PStep &d, uint32_t ns, uint
 __device__ __forceinline__ double2 grid_point(const PStep &d, const uint64_t *cidx, uint32_t nkap) {
   double2 acc = make_double2(0.0, 0.0);
   for (uint32_t kk = 0; kk < nkap; ++kk) {
-    double2 prod = load_g(d.in[0].base, d.in[0].f64, cidx[0] + d.in[0].tab[272 + kk]);
+    double2 prod = load_g(d.in[0].base, d.in[0].f64, cidx[0] + kpart(d.in[0], kk, d.rC));
 #pragma unroll
     for (int i = 1; i < kMaxIn; ++i)
-      if (i < d.nin) prod = cmul(prod, load_g(d.in[i].base, d.in[i].f64, cidx[i] + d.in[i].tab[272 + kk]));
+      if (i < d.nin) prod = cmul(prod, load_g(d.in[i].base, d.in[i].f64, cidx[i] + kpart(d.in[i], kk, d.rC)));
     acc.x += prod.x;
     acc.y += prod.y;
   }
@@ -507,11 +621,17 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
   __shared__ double2 s_coef[NKAP];
   __shared__ uint32_t red4[4];
   const uint32_t t = threadIdx.x;
-  if (t < NV * 16) s_mid[t >> 4][t & 15] = d.in[t >> 4].tab[256 + (t & 15)];
-  if (t < NV * NKAP) s_kap[t / NKAP][t % NKAP] = d.in[t / NKAP].tab[272 + t % NKAP];
-  uint32_t lo[NV];
+  const uint32_t cb = out_bits(d.rC);
+  if (t < NV * 16) s_mid[t >> 4][t & 15] = dpext((t & 15) << 8, d.in[t >> 4].mask & cb);
+  if (t < NV * NKAP) s_kap[t / NKAP][t % NKAP] = kpart(d.in[t / NKAP], t % NKAP, d.rC);
+  uint32_t lo[NV], hmask[NV], hshift[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) lo[v] = d.in[v].tab[t];
+  for (int v = 0; v < NV; ++v) {
+    const uint32_t cm = d.in[v].mask & cb;
+    lo[v] = dpext(t, cm & 255u);
+    hmask[v] = cm >> 12;
+    hshift[v] = __popc(cm & 4095u);
+  }
   const uint64_t Q = (uint64_t)nb * ns;
   const uint32_t nC = 1u << d.rC;
   // work units of the instance: jspan x 256 consecutive elements
@@ -524,7 +644,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
       double2 c = make_double2(1.0, 0.0);
 #pragma unroll
       for (int i = NV; i < kMaxIn; ++i)
-        if (i < d.nin) c = cmul(c, load_g(d.in[i].base, d.in[i].f64, I.off[i] + d.in[i].tab[272 + t]));
+        if (i < d.nin) c = cmul(c, load_g(d.in[i].base, d.in[i].f64, I.off[i] + kpart(d.in[i], t, d.rC)));
       s_coef[t] = c;
     }
     __syncthreads();
@@ -542,7 +662,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
       const uint32_t ch = j0 >> 4;
       uint32_t hoff[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) hoff[v] = dpext(ch, d.in[v].hi_mask) << d.in[v].hi_shift;
+      for (int v = 0; v < NV; ++v) hoff[v] = dpext(ch, hmask[v]) << hshift[v];
 #pragma unroll 1
       for (uint32_t jj = 0; jj < jspan; ++jj) {
         const uint32_t j = (j0 + jj) & 15u;
@@ -617,18 +737,25 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
   __shared__ double2 s_coef[NKAP];
   __shared__ uint32_t red4[4];
   const uint32_t t = threadIdx.x;
-  if (t < NV * 16) s_mid[t >> 4][t & 15] = d.in[t >> 4].tab[256 + (t & 15)];
+  const uint32_t cb = out_bits(d.rC);
+  if (t < NV * 16) s_mid[t >> 4][t & 15] = dpext((t & 15) << 8, d.in[t >> 4].mask & cb);
   if (t < NV * NKAP) {
     const OpDesc &in = d.in[t / NKAP];
-    s_kap[t / NKAP][t % NKAP] = (in.tab[272 + t % NKAP] >> in.pc) << in.nlo;
+    s_kap[t / NKAP][t % NKAP] = dpext(t % NKAP, in.mask >> d.rC) << __popc(in.mask & cb & 255u);
   }
-  uint32_t lo[NV], soff[NV];
+  uint32_t lo[NV], soff[NV], nlo[NV], nkv[NV], pc[NV], hmask[NV], hshift[NV];
   uint32_t bytes = 0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    lo[v] = d.in[v].tab[t];
+    const uint32_t cm = d.in[v].mask & cb;
+    lo[v] = dpext(t, cm & 255u);
+    nlo[v] = __popc(cm & 255u);
+    nkv[v] = __popc(d.in[v].mask >> d.rC);
+    pc[v] = __popc(cm);
+    hmask[v] = cm >> 12;
+    hshift[v] = __popc(cm & 4095u);
     soff[v] = bytes;
-    bytes += (1u << (d.in[v].nkv + d.in[v].nlo)) * (v < NF ? 8u : 16u);
+    bytes += (1u << (nkv[v] + nlo[v])) * (v < NF ? 8u : 16u);
   }
   const uint64_t Q = (uint64_t)nb * ns;
   const uint32_t rows = (1u << d.rC) >> 8;
@@ -641,7 +768,7 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
       double2 c = make_double2(1.0, 0.0);
 #pragma unroll
       for (int i = NV; i < kMaxIn; ++i)
-        if (i < d.nin) c = cmul(c, load_g(d.in[i].base, d.in[i].f64, I.off[i] + d.in[i].tab[272 + t]));
+        if (i < d.nin) c = cmul(c, load_g(d.in[i].base, d.in[i].f64, I.off[i] + kpart(d.in[i], t, d.rC)));
       s_coef[t] = c;
     }
     char *op = (char *)d.out.base + I.obase * (d.out.f64 ? 16u : 8u);
@@ -657,12 +784,11 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
         for (int v = 0; v < NV; ++v) {
           const OpDesc &in = d.in[v];
           const uint64_t rb = I.off[v] + s_mid[v][row & 15u] +
-                              ((uint64_t)dpext(row >> 4, in.hi_mask) << in.hi_shift);
-          const uint32_t nlo = in.nlo, pc = in.pc;
-          const uint32_t n = 1u << (in.nkv + nlo);
-          const uint32_t lmask = (1u << nlo) - 1u;
+                              ((uint64_t)dpext(row >> 4, hmask[v]) << hshift[v]);
+          const uint32_t n = 1u << (nkv[v] + nlo[v]);
+          const uint32_t lmask = (1u << nlo[v]) - 1u;
           for (uint32_t e = t; e < n; e += 256) {
-            const uint64_t g = rb + ((uint64_t)(e >> nlo) << pc) + (e & lmask);
+            const uint64_t g = rb + ((uint64_t)(e >> nlo[v]) << pc[v]) + (e & lmask);
             if (v < NF)
               ((float2 *)(stage + soff[v]))[e] = ((const float2 *)in.base)[g];
             else
@@ -725,7 +851,7 @@ __global__ __launch_bounds__(256) void step_small(const PStep d, uint32_t nb, ui
     uint64_t cidx[kMaxIn];
 #pragma unroll
     for (int i = 0; i < kMaxIn; ++i)
-      if (i < d.nin) cidx[i] = I.off[i] + cpart(d.in[i], c);
+      if (i < d.nin) cidx[i] = I.off[i] + cpart(d.in[i], c, rC);
     double2 acc = grid_point(d, cidx, nkap);
     if (SCALE) {
       acc.x = ldexp(acc.x, -I.sh);
@@ -744,7 +870,7 @@ __global__ __launch_bounds__(256) void step_small(const PStep d, uint32_t nb, ui
     store_g((void *)d.out.base, d.out.f64, I.obase + c, acc);
   }
 }
-constexpr int kStreamMinRank = 12;
+constexpr int kStreamMinRank = 8;
 
 // ---------------------------------------------------------------------------
 // Compensated FP64 slice sum: one block per bitstring, fixed reduction order.
@@ -897,7 +1023,12 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   int max_slots = 1;
   for (const Program &pr : X.programs) max_slots = std::max(max_slots, pr.nslots);
   const uint32_t lds_bytes = (X.lds_bytes + 15) & ~15u;
-  const uint32_t lds_total = lds_bytes + 256 * 16 + (uint32_t)(2 * max_slots + 4) * 4;
+  // ... | program descriptors (LeafStage records, kDescChunk steps)
+  uint32_t max_stage = 0;
+  for (const Program &pr : X.programs) max_stage = std::max<uint32_t>(max_stage, (uint32_t)pr.staged.size());
+  const uint32_t desc_off = (lds_bytes + 256 * 16 + (uint32_t)(2 * max_slots + 4) * 4 + 15) & ~15u;
+  const uint32_t desc_bytes = max_stage * (uint32_t)sizeof(LeafStage) + kDescChunk * (uint32_t)sizeof(PStep);
+  const uint32_t lds_total = desc_off + desc_bytes;
   if (lds_total > 160 * 1024) {
     set_error("program LDS footprint too large");
     return QTN_ESTATE;
@@ -931,20 +1062,6 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     double *lb = nullptr;
     if (int rc = upload(&lb, host, "hipMalloc(leaves)")) return rc;
     D->leafbuf = lb;
-    std::vector<uint32_t> tabs;
-    D->tab_off.assign(sch.steps.size(), {});
-    for (size_t st = 0; st < sch.steps.size(); ++st) {
-      const Step &S_ = sch.steps[st];
-      for (size_t i = 0; i < S_.in.size(); ++i) {
-        InputTables it = input_tables(S_.mask[i], S_.rC, S_.nk);
-        D->tab_off[st].push_back(tabs.size());
-        tabs.insert(tabs.end(), it.lo, it.lo + 256);
-        tabs.insert(tabs.end(), it.mid, it.mid + 16);
-        tabs.insert(tabs.end(), it.kap.begin(), it.kap.end());
-        while (tabs.size() & 63) tabs.push_back(0);
-      }
-    }
-    if (int rc = upload(&D->tabbuf, tabs, "hipMalloc(tables)")) return rc;
   }
   if (lds_total > 64 * 1024) {
     HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<true>,
@@ -952,7 +1069,29 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
   }
+  LaunchGraph lg;
+  try {
+    static const int env_streams = [] {
+      const char *e = std::getenv("QTN_STREAMS");  // tuning switch: 1 serialises every launch
+      return e ? std::max(1, std::min(1 + DeviceState::kSide, std::atoi(e))) : 1 + DeviceState::kSide;
+    }();
+    lg = launch_graph(sch, X, L, P->net.B, L.S, P->precision != QTN_FP64, env_streams);
+  } catch (const std::exception &e) {
+    set_error(e.what());
+    return QTN_ESTATE;
+  }
+  for (int k = 0; k + 1 < lg.nstreams; ++k) {
+    if (!D->side[k]) HIP_TRY(hipStreamCreateWithFlags(&D->side[k], hipStreamNonBlocking));
+    if (!D->join_ev[k]) HIP_TRY(hipEventCreateWithFlags(&D->join_ev[k], hipEventDisableTiming));
+  }
+  if (!D->fork_ev) HIP_TRY(hipEventCreateWithFlags(&D->fork_ev, hipEventDisableTiming));
+  while (D->unit_ev.size() < lg.deps.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    D->unit_ev.push_back(e);
+  }
   drop_graph(D);
+  D->lg = lg;
   D->mode = mode;
   D->ws = (char *)dev_ptr;
   D->ws_bytes = bytes;
@@ -960,6 +1099,7 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   D->max_slots = max_slots;
   D->lds_bytes = lds_bytes;
   D->lds_total = lds_total;
+  D->desc_bytes = desc_off;
   const uint64_t B = P->net.B;
   const bool scaled = P->precision != QTN_FP64;
   // algorithmic bytes and flops of each step, per instance
@@ -989,7 +1129,6 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
       o.slot = -1;
       o.f64 = 1;
       o.base = (const double *)D->leafbuf + 2 * D->leaf_elem_off[tid];
-      o.vsize = size;
       o.selmask = T.selmask;
       o.bstride = T.bdep ? (size << __builtin_popcount(T.selmask)) : 0;
     } else if (o.loc == LOC_GLOBAL) {
@@ -1029,33 +1168,18 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     for (size_t j = 0; j < ord.size(); ++j) {
       const size_t i = ord[j];
       describe(S_.in[i], d.in[j]);
-      InputTables it = input_tables(S_.mask[i], S_.rC, S_.nk);
-      d.in[j].tab = D->tabbuf + D->tab_off[st][i];
-      d.in[j].hi_mask = it.hi_mask;
-      d.in[j].hi_shift = it.hi_shift;
-      d.in[j].cvary = (S_.mask[i] & cbits) ? 1u : 0u;
-      d.in[j].pc = (uint32_t)__builtin_popcount(S_.mask[i] & cbits);
-      d.in[j].nlo = (uint32_t)__builtin_popcount(S_.mask[i] & cbits & 255u);
-      d.in[j].nkv = (uint32_t)__builtin_popcount(S_.rC >= 32 ? 0u : (S_.mask[i] >> S_.rC));
       d.in[j].mask = S_.mask[i];
-      d.nvary += (int)d.in[j].cvary;
+      d.nvary += (S_.mask[i] & cbits) ? 1 : 0;
     }
     describe(S_.out, d.out);
     d.tiled_lds = tiled_lds_bytes(d);
   }
-  // program steps, contiguous per program
-  std::vector<PStep> packed;
-  std::vector<ProgDesc> progs;
-  std::vector<LeafStage> stages;
-  for (const Program &pr : X.programs) {
-    ProgDesc pd;
-    std::memset(&pd, 0, sizeof(pd));
-    pd.step0 = (uint32_t)packed.size();
-    pd.nsteps = (uint32_t)pr.steps.size();
-    pd.bdep = pr.bdep;
-    pd.sdep = pr.sdep;
-    pd.stage0 = (uint32_t)stages.size();
-    pd.nstage = (uint32_t)pr.staged.size();
+  // program blobs: LeafStage records, then PStep descriptors
+  std::vector<char> blob;
+  D->blob_off.assign(X.programs.size(), 0);
+  for (size_t pi = 0; pi < X.programs.size(); ++pi) {
+    const Program &pr = X.programs[pi];
+    D->blob_off[pi] = blob.size();
     for (int tid : pr.staged) {
       const Tensor &T = sch.tensors[tid];
       OpDesc o;
@@ -1064,26 +1188,22 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
       std::memset(&ls, 0, sizeof(ls));
       ls.base = (const double2 *)o.base;
       ls.bstride = o.bstride;
-      ls.vsize = o.vsize;
       ls.selmask = o.selmask;
       ls.count = 1u << T.rank();
       ls.lds_off = (uint32_t)(X.off[tid] / 16);
-      stages.push_back(ls);
+      const char *pb = (const char *)&ls;
+      blob.insert(blob.end(), pb, pb + sizeof(ls));
     }
-    for (int st : pr.steps) packed.push_back(D->steps[st]);
-    progs.push_back(pd);
+    for (int st : pr.steps) {
+      const char *pb = (const char *)&D->steps[st];
+      blob.insert(blob.end(), pb, pb + sizeof(PStep));
+    }
   }
-  if (stages.empty()) stages.emplace_back();
-  if (int rc = upload(&D->stepbuf, packed, "hipMalloc(program steps)")) return rc;
-  if (int rc = upload(&D->progbuf, progs, "hipMalloc(programs)")) return rc;
-  if (int rc = upload(&D->stagebuf, stages, "hipMalloc(staged factors)")) return rc;
-  std::vector<int> pl;
-  D->group_plist_off.clear();
-  for (const LaunchGroup &g : X.launches) {
-    D->group_plist_off.push_back(pl.size());
-    if (g.kind == 0) pl.insert(pl.end(), g.programs.begin(), g.programs.end());
+  if (blob.size() > 0xffffffffull) {
+    set_error("program descriptors too large");
+    return QTN_ESTATE;
   }
-  if (int rc = upload(&D->plistbuf, pl, "hipMalloc(program lists)")) return rc;
+  if (int rc = upload(&D->blobbuf, blob, "hipMalloc(program descriptors)")) return rc;
   return QTN_OK;
 }
 
@@ -1101,7 +1221,9 @@ static uint32_t tiled_lds_bytes(const PStep &d) {
   for (int v = 0; v < d.nvary; ++v) {
     const OpDesc &in = d.in[v];
     if (in.loc != LOC_GLOBAL && in.loc != LOC_LEAF) return 0;
-    const uint64_t n = 1ull << (in.nkv + in.nlo);
+    const uint32_t cb = d.rC >= 32 ? ~0u : ((1u << d.rC) - 1u);
+    const uint64_t n = 1ull << (__builtin_popcount(d.rC >= 32 ? 0u : (in.mask >> d.rC)) +
+                                __builtin_popcount(in.mask & cb & 255u));
     staged += n;
     bytes += n * (v < d.nf32 ? 8u : 16u);
   }
@@ -1167,77 +1289,116 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
   const Tensor &res = sch.tensors[sch.result];
   const uint64_t scratch_stride = (X.scratch_per_wg + 255) & ~uint64_t(255);
   bool first = true;
+  const LaunchGraph &lg = D->lg;
+  const bool multi = lg.nstreams > 1 && !D->timing;
+  auto unit_stream = [&](int u) {
+    return (!multi || lg.stream[u] == 0) ? stream : D->side[lg.stream[u] - 1];
+  };
   for (uint64_t s_lo = lo; s_lo < hi; s_lo += S) {
     const uint64_t cnt = std::min<uint64_t>(S, hi - s_lo);
-    if (SCALE && D->L.exp_bytes) {
-      const uint64_t words = D->L.exp_bytes / 4;
-      hipLaunchKernelGGL(zero_words, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 4096)),
-                         dim3(256), 0, stream, (uint32_t *)(D->ws + D->L.data_bytes), words);
+    if (multi) {
+      // side streams start after everything before this wave
+      HIP_TRY(hipEventRecord(D->fork_ev, stream));
+      for (int k = 0; k + 1 < lg.nstreams; ++k) HIP_TRY(hipStreamWaitEvent(D->side[k], D->fork_ev, 0));
     }
-    for (size_t g = 0; g < X.launches.size(); ++g) {
-      const LaunchGroup &G = X.launches[g];
-      if (G.kind == 0) {
-        uint64_t total = 0;
-        for (int p : G.programs) {
-          const Program &pr = X.programs[p];
-          total += (pr.bdep ? B : 1) * (pr.sdep ? cnt : 1);
-        }
-        const uint64_t cap = D->mode == MODE_SLICE ? D->L.wg_slots : 2048;
-        const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
-        hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), D->lds_total,
-                           stream, (const PStep *)D->stepbuf, (const ProgDesc *)D->progbuf,
-                           (const LeafStage *)D->stagebuf,
-                           (const int *)(D->plistbuf + D->group_plist_off[g]),
-                           (uint32_t)G.programs.size(), (uint32_t)B, (uint32_t)total, s_lo,
-                           (uint32_t)cnt, D->ws + D->L.scratch_off, scratch_stride,
-                           D->lds_bytes, D->max_slots);
-      } else {
-        const int st = G.step;
-        const PStep &d = D->steps[st];
-        const uint32_t nb = sch.steps[st].bdep ? (uint32_t)B : 1;
-        const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
-        const uint64_t Q = (uint64_t)nb * ns;
-        const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
-        const bool timed = D->timing && streaming;
-        if (timed) {
-          if (D->ev_used + 2 > D->ev.size()) {
-            for (int j = 0; j < 64; ++j) {
-              hipEvent_t e;
-              HIP_TRY(hipEventCreate(&e));
-              D->ev.push_back(e);
+    const int U = (int)lg.deps.size();
+    for (int u = 0; u < U; ++u) {
+      const hipStream_t ustream = unit_stream(u);
+      if (multi)
+        for (int d : lg.deps[u])
+          if (lg.stream[d] != lg.stream[u]) HIP_TRY(hipStreamWaitEvent(ustream, D->unit_ev[d], 0));
+      {
+        const hipStream_t stream = ustream;
+        if (u == 0) {
+          if (SCALE && D->L.exp_bytes) {
+            const uint64_t words = D->L.exp_bytes / 4;
+            hipLaunchKernelGGL(zero_words, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 4096)),
+                               dim3(256), 0, stream, (uint32_t *)(D->ws + D->L.data_bytes), words);
+          }
+        } else if (u == U - 1) {
+          const uint64_t rb = res.bdep ? (res.sdep ? S : 1) : 0, rs = res.sdep ? 1 : 0;
+          hipLaunchKernelGGL((slice_sum<SCALE>), dim3((unsigned)B), dim3(256), 0, stream,
+                             (const void *)(D->ws + res.data_off), res.f64 ? 1u : 0u,
+                             (const int *)(D->ws + res.exp_off), rb, rs, (uint32_t)cnt,
+                             P->net.prefactor, partials, first ? 1 : 0);
+          first = false;
+        } else {
+          const size_t g = (size_t)(u - 1);
+          const LaunchGroup &G = X.launches[g];
+          if (G.kind == 0) {
+            // at most kMaxGroupProgs programs per launch
+            for (size_t p0 = 0; p0 < G.programs.size(); p0 += kMaxGroupProgs) {
+              GroupArgs ga;
+              std::memset(&ga, 0, sizeof(ga));
+              uint64_t total = 0;
+              for (size_t k = p0; k < G.programs.size() && k < p0 + kMaxGroupProgs; ++k) {
+                const Program &pr = X.programs[G.programs[k]];
+                const uint32_t j = ga.nprog++;
+                total += (pr.bdep ? B : 1) * (pr.sdep ? cnt : 1);
+                ga.blob_off[j] = (uint32_t)D->blob_off[G.programs[k]];
+                ga.item_end[j] = (uint32_t)total;
+                ga.nsteps[j] = (uint16_t)pr.steps.size();
+                ga.nstage[j] = (uint16_t)pr.staged.size();
+                ga.bdep[j] = pr.bdep ? 1 : 0;
+                ga.sdep[j] = pr.sdep ? 1 : 0;
+              }
+              const uint64_t cap = D->mode == MODE_SLICE ? D->L.wg_slots : 2048;
+              const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
+              hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), D->lds_total,
+                                 stream, (const char *)D->blobbuf, ga, (uint32_t)B, (uint32_t)total, s_lo,
+                                 (uint32_t)cnt, D->ws + D->L.scratch_off, scratch_stride,
+                                 D->lds_bytes, D->max_slots, D->desc_bytes);
+            }
+          } else {
+            const int st = G.step;
+            const PStep &d = D->steps[st];
+            const uint32_t nb = sch.steps[st].bdep ? (uint32_t)B : 1;
+            const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
+            const uint64_t Q = (uint64_t)nb * ns;
+            const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
+            const bool timed = D->timing && streaming;
+            if (timed) {
+              if (D->ev_used + 2 > D->ev.size()) {
+                for (int j = 0; j < 64; ++j) {
+                  hipEvent_t e;
+                  HIP_TRY(hipEventCreate(&e));
+                  D->ev.push_back(e);
+                }
+              }
+              HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
+            }
+            if (streaming) {
+              // units of jspan x 256 elements: about 2048 blocks over the chip
+              const uint32_t rows = (1u << d.rC) >> 8;
+              uint32_t jspan = 16;
+              while (jspan > 1 && (uint64_t)(rows / jspan) * Q < 2048) jspan >>= 1;
+              const uint64_t units = rows / jspan;
+              const uint64_t want = std::max<uint64_t>(1, 4096 / std::max<uint64_t>(Q, 1));
+              const dim3 grid((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
+              launch_stream<SCALE>(d, grid, stream, nb, ns, s_lo, jspan);
+            } else {
+              const uint64_t total = Q << d.rC;
+              const unsigned blocks =
+                  (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
+              hipLaunchKernelGGL((step_small<SCALE>), dim3(blocks), dim3(256), 0, stream, d, nb, ns, s_lo);
+            }
+            if (timed) {
+              HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
+              D->ev_used += 2;
+              D->ev_bytes.push_back((double)Q * D->step_bytes[st]);
+              D->ev_flops.push_back((double)Q * D->step_flops[st]);
             }
           }
-          HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
-        }
-        if (streaming) {
-          // units of jspan x 256 elements: about 2048 blocks over the chip
-          const uint32_t rows = (1u << d.rC) >> 8;
-          uint32_t jspan = 16;
-          while (jspan > 1 && (uint64_t)(rows / jspan) * Q < 2048) jspan >>= 1;
-          const uint64_t units = rows / jspan;
-          const uint64_t want = std::max<uint64_t>(1, 4096 / std::max<uint64_t>(Q, 1));
-          const dim3 grid((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
-          launch_stream<SCALE>(d, grid, stream, nb, ns, s_lo, jspan);
-        } else {
-          const uint64_t total = Q << d.rC;
-          const unsigned blocks =
-              (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
-          hipLaunchKernelGGL((step_small<SCALE>), dim3(blocks), dim3(256), 0, stream, d, nb, ns, s_lo);
-        }
-        if (timed) {
-          HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
-          D->ev_used += 2;
-          D->ev_bytes.push_back((double)Q * D->step_bytes[st]);
-          D->ev_flops.push_back((double)Q * D->step_flops[st]);
         }
       }
+      if (multi && lg.record[u]) HIP_TRY(hipEventRecord(D->unit_ev[u], ustream));
     }
-    const uint64_t rb = res.bdep ? (res.sdep ? S : 1) : 0, rs = res.sdep ? 1 : 0;
-    hipLaunchKernelGGL((slice_sum<SCALE>), dim3((unsigned)B), dim3(256), 0, stream,
-                       (const void *)(D->ws + res.data_off), res.f64 ? 1u : 0u,
-                       (const int *)(D->ws + res.exp_off), rb, rs, (uint32_t)cnt,
-                       P->net.prefactor, partials, first ? 1 : 0);
-    first = false;
+    if (multi) {
+      for (int k = 0; k + 1 < lg.nstreams; ++k) {
+        HIP_TRY(hipEventRecord(D->join_ev[k], D->side[k]));
+        HIP_TRY(hipStreamWaitEvent(stream, D->join_ev[k], 0));
+      }
+    }
   }
   HIP_TRY(hipGetLastError());
   return QTN_OK;
