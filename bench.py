@@ -23,6 +23,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "slices/sec + amplitudes/sec, n=120 p=1 3-reg QAOA, mixed-prec vs FP64 GPU"
 HBM_PEAK_GBS = 8000.0
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP64_VECTOR_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 CSRC = os.path.join(ROOT, "paper_2010_14962_amd", "csrc")
 
 
@@ -36,11 +38,16 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per streaming-kernel launch from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when
-    the kernels changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_step_stream_%s.md" % workload)
+def kernel_file_tag(kernel: str) -> str:
+    """File-name form of a kernel instance name, e.g. step_tiled_true_4_3_3."""
+    return "".join(c if c.isalnum() else "_" for c in kernel).replace("__", "_").strip("_")
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE runs, copy-calibrated), or None when the
+    kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel_file_tag(kernel), workload))
     if not os.path.exists(path):
         return None
     vals = {}
@@ -176,6 +183,7 @@ def main():
         el = time.perf_counter() - t
         tm = plan.timing() if timing else None
         if timing:
+            tm["steps"] = {st: plan.step_timing(st) for st in range(plan.info()["n_steps"])}
             plan.set_timing(False)
         plan.set_graphs(True)
         return el, [p.value() for p in out], tm
@@ -185,7 +193,8 @@ def main():
     print("# mixed: %.3f ms/step" % (1e3 * el / args.steps), file=sys.stderr, flush=True)
     # roofline: same contraction, direct launches with per-launch events
     el_t, _, tm = run(mixed, args.steps, 1, True)
-    print("# mixed, direct launches with events: %.3f ms/step; %s" % (1e3 * el_t / args.steps, tm),
+    print("# mixed, direct launches with events: %.3f ms/step; %s" %
+          (1e3 * el_t / args.steps, {k: v for k, v in tm.items() if k != "steps"}),
           file=sys.stderr, flush=True)
     n64 = args.fp64_steps or max(3, args.steps // 2)
     el64, amps64, _ = run(f64, n64, 2, False)
@@ -198,15 +207,33 @@ def main():
 
     roof = None
     if tm and tm["launches"]:
-        avg_ms = tm["total_ms"] / tm["launches"]
-        bytes_per_launch = tm["alg_bytes"] / tm["launches"]
-        achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        roof = {"kernel": "step_stream<true, *> (rescaled streaming steps, all instances)",
-                "bound": "hbm", "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(args.workload), "launches": tm["launches"], "avg_launch_us": 1e3 * avg_ms,
-                "alg_bytes_per_launch": bytes_per_launch,
-                "time_share": tm["total_ms"] / (1e3 * el_t)}
+        # dominant kernel: the grid-wide step with the largest timed share
+        per = [(t, st) for st, t in tm["steps"].items() if t["launches"]]
+        t, st = max(per, key=lambda x: x[0]["total_ms"])
+        kern = mixed.step_kernel(st)
+        avg_ms = t["total_ms"] / t["launches"]
+        bytes_per_launch = t["alg_bytes"] / t["launches"]
+        flops_per_launch = t["alg_flops"] / t["launches"]
+        gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        tfs = flops_per_launch / (avg_ms * 1e-3) / 1e12
+        f_hbm, f_alu = gbs / HBM_PEAK_GBS, tfs / FP64_VECTOR_PEAK_TFLOPS
+        if f_alu > f_hbm:
+            bound, achieved, peak, unit = "alu", tfs, FP64_VECTOR_PEAK_TFLOPS, "TFLOP/s"
+        else:
+            bound, achieved, peak, unit = "hbm", gbs, HBM_PEAK_GBS, "GB/s"
+        traffic = measured_traffic(args.workload, kern)
+        roof = {"kernel": "%s (schedule step %d, all %d instances in one launch)" % (kern, st, B),
+                "bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
+                "frac": achieved / peak, "traffic": traffic,
+                "launches": t["launches"], "avg_launch_us": 1e3 * avg_ms,
+                "alg_bytes_per_launch": bytes_per_launch, "alg_flops_per_launch": flops_per_launch,
+                "hbm_GBs": gbs, "hbm_frac": f_hbm, "fp64_TFLOPs": tfs, "fp64_frac": f_alu,
+                "traffic_over_alg_bytes": (traffic / bytes_per_launch) if traffic else None,
+                "time_share": t["total_ms"] / (1e3 * el_t),
+                "streaming_family": {"launches": tm["launches"],
+                                     "avg_launch_us": 1e3 * tm["total_ms"] / tm["launches"],
+                                     "GBs": tm["alg_bytes"] / (tm["total_ms"] * 1e-3) / 1e9,
+                                     "time_share": tm["total_ms"] / (1e3 * el_t)}}
 
     line = {
         "metric": METRIC, "value": amps_per_s, "unit": "amplitudes/s", "n_gpus": 1,

@@ -211,14 +211,18 @@ int qtn_contract(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi,
  */
 int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
 
-/* Accumulated timing of the streaming step kernel (steps whose output holds
- * at least 2^12 elements per instance), measured with HIP events recorded on
- * the contraction stream around each of its launches. */
+/* Accumulated timing of the streaming step kernels (grid-wide steps whose
+ * output holds at least 2^8 elements per instance: step_stream and
+ * step_tiled), measured with HIP events recorded on the launch's stream
+ * around each launch.  While timing is on, every launch runs on the caller's
+ * stream in schedule order, so that the events bracket one kernel each. */
 typedef struct {
   uint64_t launches;
   double total_ms;   /* summed launch durations                              */
   double alg_bytes;  /* algorithmic bytes: every input read once, output once */
-  double alg_flops;  /* real flops of the complex products and sums           */
+  double alg_flops;  /* real flops: per step index point, 6 per complex product
+                        of the varying operands and the kappa coefficient,
+                        plus 2 for the accumulation                          */
   uint64_t dropped;  /* launches whose event pair could not be read           */
   int32_t last_error;/* HIP error of the last unreadable pair (0 if none)     */
 } qtn_kernel_timing;
@@ -229,6 +233,16 @@ int qtn_plan_set_timing(qtn_plan_t *plan, int enable);
 
 /* Reads the counters accumulated by qtn_contract calls since the last reset. */
 int qtn_plan_timing(const qtn_plan_t *plan, qtn_kernel_timing *out);
+
+/* The same counters restricted to schedule step `step` (zero if the step
+ * was not timed). */
+int qtn_plan_step_timing(const qtn_plan_t *plan, int32_t step, qtn_kernel_timing *out);
+
+/* Name of the kernel instance that runs grid-wide step `step` under the
+ * bound workspace, e.g. "step_tiled<true, 4, 3, 3>" (rescaled, 4 summed
+ * variables, 3 varying operands of which 3 complex64); "" for steps run
+ * inside workgroup programs.  NUL-terminated, truncated to `capacity`. */
+int qtn_plan_step_kernel(const qtn_plan_t *plan, int32_t step, char *name, uint32_t capacity);
 
 /* ---------------------------------------------------------------------------
  * Learned cut-set cost model.  Not part of the paper: it ranks candidate cut

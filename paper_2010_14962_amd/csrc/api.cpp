@@ -341,7 +341,22 @@ extern "C" int qtn_plan_workspace_bytes(const qtn_plan_t *P, uint64_t S, uint64_
   try {
     Layout L = layout(copy, P->exec[mode], P->net.B, S, wg_slots_for(P, mode, S));
     // the stream assignment of the launches checks itself as well
-    (void)launch_graph(copy, P->exec[mode], L, P->net.B, S, P->precision != QTN_FP64, 4);
+    LaunchGraph lg = launch_graph(copy, P->exec[mode], L, P->net.B, S, P->precision != QTN_FP64, 4);
+    if (const char *e = std::getenv("QTN_PLAN_REPORT"); e && e[0] == '1') {
+      const ExecPlan &X = P->exec[mode];
+      std::fprintf(stderr, "qtn launch graph (S=%llu): %d streams\n", (unsigned long long)S, lg.nstreams);
+      for (size_t u = 0; u < lg.deps.size(); ++u) {
+        std::string what = u == 0 ? "clear exponents"
+                           : u + 1 == lg.deps.size() ? "slice sum"
+                           : X.launches[u - 1].kind == 0
+                               ? "programs x" + std::to_string(X.launches[u - 1].programs.size())
+                               : "step " + std::to_string(X.launches[u - 1].step);
+        std::string deps;
+        for (int d : lg.deps[u]) deps += " " + std::to_string(d);
+        std::fprintf(stderr, "  unit %2zu stream %d %-16s after:%s\n", u, lg.stream[u], what.c_str(),
+                     deps.c_str());
+      }
+    }
     *bytes = L.total_bytes;
   } catch (const std::exception &e) {
     return fail(QTN_ESTATE, e.what());

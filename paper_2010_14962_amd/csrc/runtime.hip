@@ -99,7 +99,13 @@ struct DeviceState {
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
   std::vector<double> ev_bytes, ev_flops;
+  std::vector<int> ev_step;
   double t_ms = 0, t_bytes = 0, t_flops = 0;
+  struct StepTiming {
+    uint64_t launches = 0;
+    double ms = 0, bytes = 0, flops = 0;
+  };
+  std::vector<StepTiming> t_step;  // per schedule step
   uint64_t t_launches = 0, t_failed = 0;
   int t_last_error = 0;
   std::vector<double> step_bytes, step_flops;  // per instance of each step
@@ -121,6 +127,7 @@ struct DeviceState {
   bool g_timing = false;
   size_t g_ev_used = 0;
   std::vector<double> g_ev_bytes, g_ev_flops;
+  std::vector<int> g_ev_step;
 };
 
 static void drop_graph(DeviceState *d) {
@@ -1110,8 +1117,14 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     double by = std::ldexp((double)elem_bytes(sch.tensors[S_.out]), S_.rC);
     for (int i : S_.in) by += std::ldexp((double)elem_bytes(sch.tensors[i]), sch.tensors[i].rank());
     D->step_bytes[st] = by;
-    D->step_flops[st] = std::ldexp(1.0, S_.nk + S_.rC) *
-                        (6.0 * (double)(S_.in.size() - 1) + (S_.nk > 0 ? 2.0 : 0.0));
+    // complex products per step index point: the varying operands, and one
+    // with the kappa coefficient of the uniform operands when there are any
+    const uint32_t cbits = S_.rC >= 32 ? ~0u : ((1u << S_.rC) - 1u);
+    int nvary = 0;
+    for (size_t i = 0; i < S_.in.size(); ++i) nvary += (S_.mask[i] & cbits) ? 1 : 0;
+    const int nuni = (int)S_.in.size() - nvary;
+    const int nprod = std::max(0, nvary - 1) + (nuni > 0 && nvary > 0 ? 1 : 0);
+    D->step_flops[st] = std::ldexp(1.0, S_.nk + S_.rC) * (6.0 * nprod + (S_.nk > 0 ? 2.0 : 0.0));
   }
   // operand descriptors
   auto describe = [&](int tid, OpDesc &o) {
@@ -1387,6 +1400,7 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
               D->ev_used += 2;
               D->ev_bytes.push_back((double)Q * D->step_bytes[st]);
               D->ev_flops.push_back((double)Q * D->step_flops[st]);
+              D->ev_step.push_back(st);
             }
           }
         }
@@ -1462,6 +1476,7 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
       D->ev_used = 0;
       D->ev_bytes.clear();
       D->ev_flops.clear();
+      D->ev_step.clear();
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(D->gstream, hipStreamCaptureModeThreadLocal));
       int rc = enqueue(D->gstream);
@@ -1483,6 +1498,7 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
       D->g_ev_used = D->ev_used;
       D->g_ev_bytes = D->ev_bytes;
       D->g_ev_flops = D->ev_flops;
+      D->g_ev_step = D->ev_step;
     }
     HIP_TRY(hipEventRecord(D->gdep, stream));
     HIP_TRY(hipStreamWaitEvent(D->gstream, D->gdep, 0));
@@ -1493,6 +1509,7 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
     D->ev_used = D->g_ev_used;
     D->ev_bytes = D->g_ev_bytes;
     D->ev_flops = D->g_ev_flops;
+    D->ev_step = D->g_ev_step;
   } else {
     int rc = enqueue(stream);
     if (rc) return rc;
@@ -1513,12 +1530,20 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
       D->t_ms += ms;
       D->t_bytes += D->ev_bytes[j / 2];
       D->t_flops += D->ev_flops[j / 2];
+      const int st = D->ev_step[j / 2];
+      if (st >= 0 && (size_t)st < D->t_step.size()) {
+        D->t_step[st].launches += 1;
+        D->t_step[st].ms += ms;
+        D->t_step[st].bytes += D->ev_bytes[j / 2];
+        D->t_step[st].flops += D->ev_flops[j / 2];
+      }
       D->t_launches += 1;
     }
   }
   D->ev_used = 0;
   D->ev_bytes.clear();
   D->ev_flops.clear();
+  D->ev_step.clear();
   return QTN_OK;
 }
 
@@ -1542,6 +1567,7 @@ extern "C" int qtn_plan_set_timing(qtn_plan_t *P, int enable) {
   D->t_ms = D->t_bytes = D->t_flops = 0;
   D->t_launches = D->t_failed = 0;
   D->t_last_error = 0;
+  D->t_step.assign(P->sched.steps.size(), DeviceState::StepTiming());
   return QTN_OK;
 }
 
@@ -1557,5 +1583,56 @@ extern "C" int qtn_plan_timing(const qtn_plan_t *P, qtn_kernel_timing *out) {
   out->alg_flops = D->t_flops;
   out->dropped = D->t_failed;
   out->last_error = D->t_last_error;
+  return QTN_OK;
+}
+
+extern "C" int qtn_plan_step_timing(const qtn_plan_t *P, int32_t step, qtn_kernel_timing *out) {
+  if (!P || !out || !P->dev) {
+    set_error("bind a workspace first");
+    return QTN_ESTATE;
+  }
+  if (step < 0 || (size_t)step >= P->sched.steps.size()) {
+    set_error("step out of range");
+    return QTN_ERANGE;
+  }
+  const DeviceState *D = P->dev;
+  std::memset(out, 0, sizeof(*out));
+  if ((size_t)step < D->t_step.size()) {
+    const DeviceState::StepTiming &T = D->t_step[step];
+    out->launches = T.launches;
+    out->total_ms = T.ms;
+    out->alg_bytes = T.bytes;
+    out->alg_flops = T.flops;
+  }
+  return QTN_OK;
+}
+
+extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *name, uint32_t capacity) {
+  if (!P || !P->dev || !name || capacity == 0) {
+    set_error("bind a workspace first");
+    return QTN_ESTATE;
+  }
+  if (step < 0 || (size_t)step >= P->sched.steps.size()) {
+    set_error("step out of range");
+    return QTN_ERANGE;
+  }
+  const DeviceState *D = P->dev;
+  const ExecPlan &X = P->exec[D->mode];
+  std::string k;
+  for (const LaunchGroup &G : X.launches)
+    if (G.kind == 1 && G.step == step) {
+      const PStep &d = D->steps[step];
+      const bool sc = P->precision != QTN_FP64;
+      const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
+      const std::string tf = sc ? "true" : "false";
+      if (!streaming)
+        k = "step_small<" + tf + ">";
+      else
+        k = std::string(d.tiled_lds ? "step_tiled<" : "step_stream<") + tf + ", " +
+            std::to_string(d.nk) + ", " + std::to_string(d.nvary) + ", " +
+            std::to_string(d.nf32 <= d.nvary ? d.nf32 : 0) + ">";
+    }
+  std::strncpy(name, k.c_str(), capacity - 1);
+  name[capacity - 1] = 0;
   return QTN_OK;
 }

@@ -78,7 +78,8 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_plan_set_timing", "qtn_plan_timing", "qtn_plan_set_graphs", "qtn_last_error",
            "qtn_cost_features", "qtn_cost_exact", "qtn_mlp_create", "qtn_mlp_destroy",
            "qtn_mlp_num_params", "qtn_mlp_get_params", "qtn_mlp_set_params", "qtn_mlp_get_grads",
-           "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search"]
+           "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search",
+           "qtn_plan_step_timing", "qtn_plan_step_kernel"]
 COST_FEATURES = 32
 
 
@@ -115,6 +116,8 @@ def lib():
     L.qtn_plan_set_timing.argtypes = [c_void_p, c_int32]
     L.qtn_plan_set_graphs.argtypes = [c_void_p, c_int32]
     L.qtn_plan_timing.argtypes = [c_void_p, POINTER(QtnKernelTiming)]
+    L.qtn_plan_step_timing.argtypes = [c_void_p, c_int32, POINTER(QtnKernelTiming)]
+    L.qtn_plan_step_kernel.argtypes = [c_void_p, c_int32, c_char_p, c_uint32]
     L.qtn_last_error.argtypes = []
     L.qtn_last_error.restype = c_char_p
     pf, pu32 = POINTER(ctypes.c_float), POINTER(c_uint32)
@@ -250,6 +253,16 @@ class Plan:
         t = QtnKernelTiming()
         _check(lib().qtn_plan_timing(self._h, byref(t)))
         return {f: getattr(t, f) for f, _ in QtnKernelTiming._fields_}
+
+    def step_timing(self, step: int) -> dict:
+        t = QtnKernelTiming()
+        _check(lib().qtn_plan_step_timing(self._h, step, byref(t)))
+        return {f: getattr(t, f) for f, _ in t._fields_}
+
+    def step_kernel(self, step: int) -> str:
+        buf = ctypes.create_string_buffer(128)
+        _check(lib().qtn_plan_step_kernel(self._h, step, buf, len(buf)))
+        return buf.value.decode()
 
     def contract(self, slice_lo: int, slice_hi: int, stream: Optional[int] = None) -> List[QtnPartial]:
         out = (QtnPartial * self.n_bitstrings)()
