@@ -345,7 +345,8 @@ extern "C" int qtn_plan_workspace_bytes(const qtn_plan_t *P, uint64_t S, uint64_
     if (const char *e = std::getenv("QTN_PLAN_REPORT"); e && e[0] == '1') {
       const ExecPlan &X = P->exec[mode];
       std::fprintf(stderr, "qtn launch graph (S=%llu): %d streams\n", (unsigned long long)S, lg.nstreams);
-      for (size_t u = 0; u < lg.deps.size(); ++u) {
+      for (size_t ui = 0; ui < lg.deps.size(); ++ui) {
+        const size_t u = (size_t)lg.order[ui];
         std::string what = u == 0 ? "clear exponents"
                            : u + 1 == lg.deps.size() ? "slice sum"
                            : X.launches[u - 1].kind == 0

@@ -926,19 +926,54 @@ LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, 
         if (anc[u][a]) anc[v][a] = 1;
     }
   }
-  // streams: follow the latest dependency's stream when it ends there, else
-  // take the stream whose last unit is oldest
+  // enqueue order: among ready units, the one with the longest remaining
+  // path first, a unit weighing a fixed launch latency plus its bytes
+  std::vector<double> w(U, 0.0), bottom(U, 0.0);
+  for (size_t u = 0; u < U; ++u) {
+    double by = 0;
+    for (const Range &r : rng[u]) by += (double)(r.hi - r.lo);
+    w[u] = 4.0e7 + by;
+  }
+  std::vector<std::vector<int>> succ(U);
+  for (size_t v = 0; v < U; ++v)
+    for (int u : G.deps[v]) succ[u].push_back((int)v);
+  for (size_t v = U; v-- > 0;) {
+    double m = 0;
+    for (int x : succ[v]) m = std::max(m, bottom[x]);
+    bottom[v] = w[v] + m;
+  }
+  {
+    std::vector<int> indeg(U, 0);
+    for (size_t v = 0; v < U; ++v) indeg[v] = (int)G.deps[v].size();
+    std::vector<int> ready;
+    for (size_t v = 0; v < U; ++v)
+      if (!indeg[v]) ready.push_back((int)v);
+    while (!ready.empty()) {
+      size_t bi = 0;
+      for (size_t i = 1; i < ready.size(); ++i)
+        if (bottom[ready[i]] > bottom[ready[bi]] ||
+            (bottom[ready[i]] == bottom[ready[bi]] && ready[i] < ready[bi]))
+          bi = i;
+      const int v = ready[bi];
+      ready.erase(ready.begin() + bi);
+      G.order.push_back(v);
+      for (int x : succ[v])
+        if (--indeg[x] == 0) ready.push_back(x);
+    }
+  }
+  // streams, in enqueue order: follow a dependency's stream when that
+  // dependency is the stream's last unit, else take a stream whose last unit
+  // is already an ancestor, else the one whose last unit came earliest
   const int ns = std::max(1, max_streams);
   G.stream.assign(U, 0);
   G.record.assign(U, 0);
   std::vector<int> tail(ns, -1);
-  for (size_t v = 0; v < U; ++v) {
+  std::vector<int> pos(U, 0);
+  for (size_t i = 0; i < U; ++i) pos[G.order[i]] = (int)i;
+  for (int v : G.order) {
     int pick = -1;
-    for (int u : G.deps[v])  // latest first
-      if (tail[G.stream[u]] == u) {
-        pick = G.stream[u];
-        break;
-      }
+    for (int u : G.deps[v])
+      if (tail[G.stream[u]] == u && (pick < 0 || pos[u] > pos[tail[pick]])) pick = G.stream[u];
     if (pick < 0) {
       // a stream whose last unit is already an ancestor adds no ordering
       for (int k = 0; k < ns && pick < 0; ++k)
@@ -947,21 +982,25 @@ LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, 
     if (pick < 0) {
       pick = 0;
       for (int k = 1; k < ns; ++k)
-        if (tail[k] < tail[pick]) pick = k;
+        if (pos[tail[k]] < pos[tail[pick]]) pick = k;
     }
     G.stream[v] = pick;
-    tail[pick] = (int)v;
+    tail[pick] = v;
     for (int u : G.deps[v])
       if (G.stream[u] != pick) G.record[u] = 1;
     G.nstreams = std::max(G.nstreams, pick + 1);
   }
-  // self-check: units left unordered never touch conflicting bytes
+  // self-check: units left unordered never touch conflicting bytes, and a
+  // stream never holds a unit before one it depends on
   for (size_t v = 0; v < U; ++v)
     for (size_t u = 0; u < v; ++u) {
       bool ordered = anc[v][u] != 0;
       if (!ordered && G.stream[u] == G.stream[v]) ordered = true;  // same stream: FIFO
       if (!ordered && conflict(u, v)) throw std::runtime_error("launch graph misses a dependency");
     }
+  for (size_t v = 0; v < U; ++v)
+    for (int u : G.deps[v])
+      if (pos[u] >= pos[v]) throw std::runtime_error("launch order breaks a dependency");
   return G;
 }
 

@@ -213,6 +213,7 @@ struct LaunchGraph {
   std::vector<std::vector<int>> deps;  // direct predecessors, transitively reduced
   std::vector<int> stream;             // stream of each unit (0 = the caller's)
   std::vector<char> record;            // another stream waits for this unit
+  std::vector<int> order;              // enqueue order: a topological order, longest remaining path first
   int nstreams = 1;
 };
 LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, uint64_t B,

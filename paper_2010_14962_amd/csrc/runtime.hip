@@ -51,7 +51,8 @@ struct PStep {
   int nvary;              // in[0..nvary) vary with the output element
   int nf32;               // of those, in[0..nf32) are stored as complex64
   uint32_t tiled_lds;     // > 0: run as step_tiled with this much LDS
-  int pad[2];
+  uint32_t wg_flags;      // in a workgroup program: 1 = every operand in LDS
+  int pad;
 };
 static_assert(sizeof(PStep) % 16 == 0, "PStep layout");
 
@@ -285,10 +286,14 @@ __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_re
 // rescaled: they carry their power-of-two exponent in sE[slot] and FP64 has
 // range to spare.  Outputs stored in global memory or scratch keep the
 // rescaled form of the grid steps (values times 2^-sh, maximum tracked).
-template <bool SCALE>
-__device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32_t s, const WgCtx &W) {
+// Specialised on the operand count NIN and on LDSONLY (every operand is an
+// LDS tensor or a staged gate factor), so that the operand loop is straight
+// code whose LDS reads issue together.
+template <bool SCALE, int NIN, bool LDSONLY>
+__device__ void wg_step_n(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32_t s, const WgCtx &W) {
+  constexpr int kMaxIn = NIN;   // the loops below cover exactly the operands
   const uint32_t t = threadIdx.x;
-  const int nin = (int)uni((uint32_t)st.nin), rC = (int)uni((uint32_t)st.rC), nk = (int)uni((uint32_t)st.nk);
+  const int nin = NIN, rC = (int)uni((uint32_t)st.rC), nk = (int)uni((uint32_t)st.nk);
   // operand keys, read in one batch
   uint32_t mk[kMaxIn], ok[kMaxIn], mt[kMaxIn];
 #pragma unroll
@@ -299,7 +304,7 @@ __device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32
   }
   const uint32_t omt = *(const QTN_LDS uint32_t *)&st.out.slot;
   const uint32_t ooff = uni(st.out.off);
-  bool all_lds = true;
+  const bool all_lds = LDSONLY;
   uint32_t lo[kMaxIn], loff[kMaxIn], hm[kMaxIn], hs[kMaxIn];
 #pragma unroll
   for (int i = 0; i < kMaxIn; ++i) {
@@ -311,7 +316,6 @@ __device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32
     hm[i] = m >> 8;
     hs[i] = __popc(m & 255u);
     loff[i] = used ? uni(ok[i]) / 16 : 0u;
-    if (used && ((mt[i] >> 16) & 255u) != LOC_LDS) all_lds = false;
   }
   const bool wide_idx = rC + nk > 8;   // else every step index fits in the low 8 bits
   // operands outside the LDS
@@ -458,6 +462,24 @@ __device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32
     }
   }
   __syncthreads();
+}
+
+template <bool SCALE>
+__device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32_t s, const WgCtx &W) {
+  const uint32_t nin = uni((uint32_t)st.nin);
+  const bool lds_only = (uni((uint32_t)st.wg_flags) & 1u) != 0;
+#define QTN_WG(N)                                      \
+  case N:                                              \
+    if (lds_only)                                      \
+      wg_step_n<SCALE, N, true>(st, b, sl, s, W);     \
+    else                                               \
+      wg_step_n<SCALE, N, false>(st, b, sl, s, W);    \
+    break;
+  switch (nin) {
+    QTN_WG(1) QTN_WG(2) QTN_WG(3) QTN_WG(4) QTN_WG(5) QTN_WG(6) QTN_WG(7) QTN_WG(8)
+    default: break;
+  }
+#undef QTN_WG
 }
 
 // Copies the gate factors of a program into LDS for instance (b, s).  Wave w
@@ -1208,7 +1230,11 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
       blob.insert(blob.end(), pb, pb + sizeof(ls));
     }
     for (int st : pr.steps) {
-      const char *pb = (const char *)&D->steps[st];
+      PStep ps = D->steps[st];
+      bool lds_only = true;
+      for (int i = 0; i < ps.nin; ++i) lds_only = lds_only && ps.in[i].loc == LOC_LDS;
+      ps.wg_flags = lds_only ? 1u : 0u;
+      const char *pb = (const char *)&ps;
       blob.insert(blob.end(), pb, pb + sizeof(PStep));
     }
   }
@@ -1315,7 +1341,9 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
       for (int k = 0; k + 1 < lg.nstreams; ++k) HIP_TRY(hipStreamWaitEvent(D->side[k], D->fork_ev, 0));
     }
     const int U = (int)lg.deps.size();
-    for (int u = 0; u < U; ++u) {
+    for (int ui = 0; ui < U; ++ui) {
+      // timing keeps the schedule order on one stream
+      const int u = multi ? lg.order[ui] : ui;
       const hipStream_t ustream = unit_stream(u);
       if (multi)
         for (int d : lg.deps[u])
