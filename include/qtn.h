@@ -82,7 +82,7 @@ typedef struct {
   int32_t ga_iters;          /* T of Algorithm 1 (default 4)                               */
   int32_t precision;         /* QTN_FP64, QTN_FP32 or QTN_3XBF16                           */
   int32_t fuse_chains;       /* 1: sum chains of trivial buckets in one step (default 1)   */
-  int32_t exec_mode;         /* -1 auto, 0 grid-wide steps, 1 one workgroup per instance  */
+  int32_t exec_mode;         /* -1 auto (= 0), 0 grid-wide steps, 1 one workgroup per instance */
 } qtn_plan_opts;
 
 typedef struct {

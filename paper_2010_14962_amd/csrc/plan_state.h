@@ -10,7 +10,7 @@ namespace qtn {
 struct DeviceState;  // defined by the HIP runtime
 constexpr uint32_t kLdsBudget = 56 * 1024;   // LDS bytes for program tensors
 constexpr uint64_t kMaxWorkgroups = 1024;    // persistent workgroups of a program launch
-constexpr uint64_t kMaxScratchTotal = 64ull << 30;
+
 // Execution mode for `slices_per_wave` slices: one workgroup per instance
 // (MODE_SLICE) when there are enough instances to fill the chip and their
 // scratch fits, else grid-wide streaming steps (MODE_WIDE).

@@ -206,3 +206,45 @@ def test_graph_replays_match_eager(mode):
     part = [(p.re, p.im) for p in g.contract(3, 200, _stream())]
     ref2 = [(p.re, p.im) for p in eager.contract(3, 200, _stream())]
     assert part == ref2
+
+
+def test_concurrent_streams_match_serial_launches():
+    """Independent launches run on several streams (graph replay and direct
+    launches); with timing on, every launch runs in schedule order on the
+    caller's stream.  All three give the same partials bit for bit."""
+    inst = workload_instance("qaoa_n120_p1_b8")
+    plan = plan_instance(inst, k=-1, max_rank=26, precision="fp32")
+    plan.bind_torch(1)
+    key = lambda out: [(p.re, p.im, p.re_comp, p.im_comp) for p in out]
+    plan.set_graphs(True)
+    replay = key(plan.contract(0, 1, _stream()))
+    plan.set_graphs(False)
+    direct = key(plan.contract(0, 1, _stream()))
+    plan.set_timing(True)
+    serial = key(plan.contract(0, 1, _stream()))
+    t = plan.timing()
+    plan.set_timing(False)
+    assert replay == direct == serial
+    assert t["launches"] > 0 and t["dropped"] == 0
+
+
+def test_step_timing_and_kernel_names():
+    """Per-step timing covers exactly the timed launches, and every grid-wide
+    step reports the kernel instance that runs it."""
+    inst = workload_instance("qaoa_n120_p1_b8")
+    plan = plan_instance(inst, k=-1, max_rank=26, precision="fp32")
+    plan.bind_torch(1)
+    plan.set_graphs(False)
+    plan.set_timing(True)
+    for _ in range(2):
+        plan.contract(0, 1, _stream())
+    total = plan.timing()
+    per = [plan.step_timing(st) for st in range(plan.info()["n_steps"])]
+    plan.set_timing(False)
+    assert sum(p["launches"] for p in per) == total["launches"]
+    assert abs(sum(p["total_ms"] for p in per) - total["total_ms"]) <= 1e-9 * max(1.0, total["total_ms"])
+    timed = [st for st, p in enumerate(per) if p["launches"]]
+    assert timed and all(per[st]["launches"] == 2 for st in timed)
+    for st in timed:
+        name = plan.step_kernel(st)
+        assert name.startswith(("step_stream<true", "step_tiled<true")), name
