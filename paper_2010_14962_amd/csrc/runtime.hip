@@ -52,7 +52,8 @@ struct PStep {
   int nf32;               // of those, in[0..nf32) are stored as complex64
   uint32_t tiled_lds;     // > 0: run as step_tiled with this much LDS
   uint32_t wg_flags;      // in a workgroup program: 1 = every operand in LDS
-  int pad;
+  int tiled_fold;         // step_tiled: operand staged as complex128 times the
+                          // kappa coefficient, or -1
 };
 static_assert(sizeof(PStep) % 16 == 0, "PStep layout");
 
@@ -261,6 +262,9 @@ extern __shared__ __align__(16) char wg_smem[];
 // LDS-qualified pointee types, so that every access compiles to an LDS
 // instruction rather than a generic (flat) one.
 #define QTN_LDS __attribute__((address_space(3)))
+
+// complex128 in LDS as one 16-byte vector (a single ds_read_b128/ds_write_b128)
+typedef double lds_c128 __attribute__((ext_vector_type(2)));
 
 // complex128 values in LDS as (re, im) pairs of doubles
 __device__ __forceinline__ double2 lds_ld(const QTN_LDS double *p, uint32_t i) {
@@ -756,7 +760,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
 // low output bits at the bottom of the operand index).  The block stages
 // those runs in LDS once per row and sums over kappa from LDS, so each
 // operand element is fetched once per row instead of once per use.
-template <bool SCALE, int NK, int NV, int NF>
+template <bool SCALE, int NK, int NV, int NF, bool FOLD>
 __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, uint32_t ns,
                                                   uint64_t s_lo, uint32_t jspan) {
   constexpr uint32_t NKAP = 1u << NK;
@@ -784,8 +788,9 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
     hmask[v] = cm >> 12;
     hshift[v] = __popc(cm & 4095u);
     soff[v] = bytes;
-    bytes += (1u << (nkv[v] + nlo[v])) * (v < NF ? 8u : 16u);
+    bytes += (1u << (nkv[v] + nlo[v])) * (v < NF && !(FOLD && v == 0) ? 8u : 16u);
   }
+  constexpr int fold = FOLD ? 0 : -1;
   const uint64_t Q = (uint64_t)nb * ns;
   const uint32_t rows = (1u << d.rC) >> 8;
   const uint32_t units = rows / jspan;
@@ -816,30 +821,53 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
                               ((uint64_t)dpext(row >> 4, hmask[v]) << hshift[v]);
           const uint32_t n = 1u << (nkv[v] + nlo[v]);
           const uint32_t lmask = (1u << nlo[v]) - 1u;
-          for (uint32_t e = t; e < n; e += 256) {
-            const uint64_t g = rb + ((uint64_t)(e >> nlo[v]) << pc[v]) + (e & lmask);
-            if (v < NF)
-              ((float2 *)(stage + soff[v]))[e] = ((const float2 *)in.base)[g];
-            else
-              ((double2 *)(stage + soff[v]))[e] = ((const double2 *)in.base)[g];
+          if (v == fold) {
+            // complex128 copy times the kappa coefficient of its run
+            QTN_LDS lds_c128 *dst = (QTN_LDS lds_c128 *)(stage + soff[v]);
+            for (uint32_t e = t; e < n; e += 256) {
+              const uint64_t g = rb + ((uint64_t)(e >> nlo[v]) << pc[v]) + (e & lmask);
+              double2 x;
+              if (v < NF) {
+                const float2 f = ((const float2 *)in.base)[g];
+                x = make_double2((double)f.x, (double)f.y);
+              } else {
+                x = ((const double2 *)in.base)[g];
+              }
+              x = cmul(x, s_coef[e >> nlo[v]]);
+              lds_c128 c;
+              c.x = x.x;
+              c.y = x.y;
+              dst[e] = c;
+            }
+          } else {
+            for (uint32_t e = t; e < n; e += 256) {
+              const uint64_t g = rb + ((uint64_t)(e >> nlo[v]) << pc[v]) + (e & lmask);
+              if (v < NF)
+                ((float2 *)(stage + soff[v]))[e] = ((const float2 *)in.base)[g];
+              else
+                ((double2 *)(stage + soff[v]))[e] = ((const double2 *)in.base)[g];
+            }
           }
         }
         __syncthreads();
         double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 4
         for (uint32_t k = 0; k < NKAP; ++k) {
-          double2 prod = s_coef[k];
+          double2 prod = fold < 0 ? s_coef[k] : make_double2(1.0, 0.0);
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             const uint32_t idx = s_kap[v][k] + lo[v];
             double2 x;
-            if (v < NF) {
+            if (v == fold) {
+              const lds_c128 c = ((const QTN_LDS lds_c128 *)(stage + soff[v]))[idx];
+              x = make_double2(c.x, c.y);
+            } else if (v < NF) {
               const float2 f = ((const float2 *)(stage + soff[v]))[idx];
               x = make_double2((double)f.x, (double)f.y);
             } else {
               x = ((const double2 *)(stage + soff[v]))[idx];
             }
-            prod = cmul(prod, x);
+            prod = (v == 0 && fold >= 0) ? x : cmul(prod, x);
           }
           acc.x += prod.x;
           acc.y += prod.y;
@@ -1207,6 +1235,11 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
       d.nvary += (S_.mask[i] & cbits) ? 1 : 0;
     }
     describe(S_.out, d.out);
+    // the first varying operand carrying every summed bit takes the
+    // coefficient of the uniform operands (only operand 0, so that the
+    // product chain starts from it)
+    d.tiled_fold = (d.nk > 0 && d.nin > d.nvary &&
+                    __builtin_popcount(S_.rC >= 32 ? 0u : (d.in[0].mask >> S_.rC)) == d.nk) ? 0 : -1;
     d.tiled_lds = tiled_lds_bytes(d);
   }
   // program blobs: LeafStage records, then PStep descriptors
@@ -1264,7 +1297,7 @@ static uint32_t tiled_lds_bytes(const PStep &d) {
     const uint64_t n = 1ull << (__builtin_popcount(d.rC >= 32 ? 0u : (in.mask >> d.rC)) +
                                 __builtin_popcount(in.mask & cb & 255u));
     staged += n;
-    bytes += n * (v < d.nf32 ? 8u : 16u);
+    bytes += n * (v < d.nf32 && v != d.tiled_fold ? 8u : 16u);
   }
   const uint64_t direct = (uint64_t)d.nvary * 256u << d.nk;
   if (3 * staged > direct || bytes > 48 * 1024) return 0;
@@ -1280,8 +1313,11 @@ static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint
   case F:                                                                                          \
     if constexpr (F <= NV)                                                                         \
     {                                                                                              \
-      if (d.tiled_lds)                                                                             \
-        hipLaunchKernelGGL((step_tiled<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256),        \
+      if (d.tiled_lds && d.tiled_fold == 0)                                                        \
+        hipLaunchKernelGGL((step_tiled<SCALE, NK, NV, (F <= NV ? F : 0), true>), grid, dim3(256),  \
+                           d.tiled_lds, stream, d, nb, ns, s_lo, jspan);                           \
+      else if (d.tiled_lds)                                                                        \
+        hipLaunchKernelGGL((step_tiled<SCALE, NK, NV, (F <= NV ? F : 0), false>), grid, dim3(256), \
                            d.tiled_lds, stream, d, nb, ns, s_lo, jspan);                           \
       else                                                                                         \
         hipLaunchKernelGGL((step_stream<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256), 0,    \
@@ -1658,7 +1694,8 @@ extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *nam
       else
         k = std::string(d.tiled_lds ? "step_tiled<" : "step_stream<") + tf + ", " +
             std::to_string(d.nk) + ", " + std::to_string(d.nvary) + ", " +
-            std::to_string(d.nf32 <= d.nvary ? d.nf32 : 0) + ">";
+            std::to_string(d.nf32 <= d.nvary ? d.nf32 : 0) +
+            (d.tiled_lds ? (d.tiled_fold == 0 ? ", true>" : ", false>") : ">");
     }
   std::strncpy(name, k.c_str(), capacity - 1);
   name[capacity - 1] = 0;
