@@ -157,8 +157,8 @@ extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
           int nleaf = 0;
           for (int st : pr.steps)
             for (int in : P->sched.steps[st].in) nleaf += P->sched.tensors[in].leaf ? 1 : 0;
-          std::fprintf(stderr, "  program %zu: %zu steps, %zu of %d factors staged, LDS %u B\n", i,
-                       pr.steps.size(), pr.staged.size(), nleaf, pr.lds_bytes);
+          std::fprintf(stderr, "  program %zu: %zu steps, %zu of %d factors and %zu workspace tensors staged, LDS %u B\n",
+                       i, pr.steps.size(), pr.staged.size(), nleaf, pr.staged_global.size(), pr.lds_bytes);
         }
       }
     }

@@ -645,12 +645,14 @@ ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget) {
         }
       }
     }
-    // Gate factors the program reads are staged in LDS at its start where
-    // they fit: each is live from the start to its consuming step.
+    // Gate factors and workspace tensors made by earlier launches are staged
+    // in LDS at the program's start where they fit: each is live from the
+    // start to its consuming step.
     uint64_t top = lds.peak;
     for (size_t si = 0; si < P.steps.size(); ++si)
       for (int i : s.steps[P.steps[si]].in) {
-        if (!s.tensors[i].leaf) continue;
+        const bool outside = !s.tensors[i].leaf && !mine[i] && x.loc[i] == LOC_GLOBAL;
+        if (!s.tensors[i].leaf && !outside) continue;
         const uint64_t size = (uint64_t)16 << s.tensors[i].rank();
         std::vector<uint64_t> cand{0};
         for (const Iv &v : ivs)
@@ -666,9 +668,15 @@ ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget) {
             }
           if (!ok) continue;
           ivs.push_back({c, size, -1, (int)si});
-          x.loc[i] = LOC_LDS;
-          x.off[i] = c;
-          P.staged.push_back(i);
+          if (outside) {
+            // the tensor stays in the workspace for its producer; only this
+            // program reads its LDS copy
+            P.staged_global.push_back({i, c, slots++});
+          } else {
+            x.loc[i] = LOC_LDS;
+            x.off[i] = c;
+            P.staged.push_back(i);
+          }
           top = std::max(top, c + size);
           break;
         }

@@ -152,6 +152,14 @@ struct Program {
   uint64_t scratch_bytes = 0;   // per-workgroup global scratch
   int nslots = 0;               // program-local exponent slots
   std::vector<int> staged;      // gate factors copied to LDS at program start
+  // workspace tensors made outside the program that it copies to LDS
+  // (complex128) at its start: tensor id, LDS byte offset, exponent slot
+  struct StagedGlobal {
+    int tensor;
+    uint64_t off;
+    int slot;
+  };
+  std::vector<StagedGlobal> staged_global;
 };
 
 struct LaunchGroup {

@@ -57,14 +57,23 @@ struct PStep {
 };
 static_assert(sizeof(PStep) % 16 == 0, "PStep layout");
 
-// One gate factor a program stages in LDS: the variant of instance (b, s)
-// is base + b * bstride + pext(s, selmask) * count, count complex128 values.
+// One tensor a program stages in LDS at its start (as complex128):
+//  * a gate factor: the variant of instance (b, s) is
+//    base + b * bstride + pext(s, selmask) * count, count complex128 values;
+//  * a workspace tensor made by an earlier launch: base + b * bstride +
+//    sl * sstride, complex64 or complex128; in the rescaled form its
+//    exponent E[b * ebstride + sl * esstride] goes to the program's slot.
 struct LeafStage {
-  const double2 *base;
-  uint64_t bstride;
-  uint32_t selmask, count, lds_off, pad;
+  const void *base;
+  uint64_t bstride, sstride;
+  const int *E;
+  uint32_t selmask, count, lds_off;
+  uint32_t ebstride, esstride;
+  int16_t slot;
+  uint8_t f64, global;
+  uint32_t pad[2];
 };
-static_assert(sizeof(LeafStage) == 32, "LeafStage layout");
+static_assert(sizeof(LeafStage) == 64, "LeafStage layout");
 
 // A program in device memory is one blob: its LeafStage records, then its
 // PStep descriptors.  A launch of workgroup programs names up to
@@ -486,10 +495,11 @@ __device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32
 #undef QTN_WG
 }
 
-// Copies the gate factors of a program into LDS for instance (b, s).  Wave w
-// takes factors w, w+4, ...; eight loads are in flight before any store.
-__device__ void stage_leaves(const QTN_LDS LeafStage *ls, uint32_t n, uint32_t b, uint32_t s,
-                             QTN_LDS double *lds) {
+// Copies the staged tensors of a program into LDS for instance (b, sl, s).
+// Wave w takes records w, w+4, ...; eight loads are in flight before any
+// store.
+__device__ void stage_leaves(const QTN_LDS LeafStage *ls, uint32_t n, uint32_t b, uint32_t sl,
+                             uint32_t s, QTN_LDS double *lds, QTN_LDS int *sE) {
   constexpr int G = 8;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -502,12 +512,31 @@ __device__ void stage_leaves(const QTN_LDS LeafStage *ls, uint32_t n, uint32_t b
       const uint32_t j = j0 + r;
       if (j < n) {
         const QTN_LDS LeafStage &L = ls[j];
-        const double2 *src = L.base + b * L.bstride + (uint64_t)dpext(s, L.selmask) * L.count;
-        if (lane < L.count) {
-          v[r] = src[lane];
-          dst[r] = L.lds_off + lane;
+        const uint32_t count = L.count, off = L.lds_off;
+        if (L.global) {
+          const uint64_t o = (uint64_t)b * L.bstride + (uint64_t)sl * L.sstride;
+          const bool f64 = L.f64 != 0;
+          const void *base = L.base;
+          auto load = [&](uint32_t i) -> double2 {
+            if (f64) return ((const double2 *)base)[o + i];
+            const float2 f = ((const float2 *)base)[o + i];
+            return make_double2((double)f.x, (double)f.y);
+          };
+          if (lane < count) {
+            v[r] = load(lane);
+            dst[r] = off + lane;
+          }
+          for (uint32_t i = lane + 64; i < count; i += 64) lds_st(lds, off + i, load(i));
+          if (lane == 0 && L.E) sE[L.slot] = L.E[b * L.ebstride + sl * L.esstride];
+        } else {
+          const double2 *src = (const double2 *)L.base + b * L.bstride +
+                               (uint64_t)dpext(s, L.selmask) * count;
+          if (lane < count) {
+            v[r] = src[lane];
+            dst[r] = off + lane;
+          }
+          for (uint32_t i = lane + 64; i < count; i += 64) lds_st(lds, off + i, src[i]);
         }
-        for (uint32_t i = lane + 64; i < L.count; i += 64) lds_st(lds, L.lds_off + i, src[i]);
       }
     }
 #pragma unroll
@@ -574,7 +603,7 @@ __global__ __launch_bounds__(256) void wg_programs(const char *__restrict__ blob
     copy_to_lds(desc, blob, lsb + min(nst, (uint32_t)kDescChunk) * (uint32_t)sizeof(PStep));
     __syncthreads();
     if (nstg) {
-      stage_leaves((const QTN_LDS LeafStage *)desc, nstg, b, s, W.lds);
+      stage_leaves((const QTN_LDS LeafStage *)desc, nstg, b, sl, s, W.lds, W.sE);
       __syncthreads();
     }
     const QTN_LDS PStep *ps = (const QTN_LDS PStep *)(desc + lsb);
@@ -1082,7 +1111,8 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   const uint32_t lds_bytes = (X.lds_bytes + 15) & ~15u;
   // ... | program descriptors (LeafStage records, kDescChunk steps)
   uint32_t max_stage = 0;
-  for (const Program &pr : X.programs) max_stage = std::max<uint32_t>(max_stage, (uint32_t)pr.staged.size());
+  for (const Program &pr : X.programs)
+    max_stage = std::max<uint32_t>(max_stage, (uint32_t)(pr.staged.size() + pr.staged_global.size()));
   const uint32_t desc_off = (lds_bytes + 256 * 16 + (uint32_t)(2 * max_slots + 4) * 4 + 15) & ~15u;
   const uint32_t desc_bytes = max_stage * (uint32_t)sizeof(LeafStage) + kDescChunk * (uint32_t)sizeof(PStep);
   const uint32_t lds_total = desc_off + desc_bytes;
@@ -1254,16 +1284,48 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
       describe(tid, o);
       LeafStage ls;
       std::memset(&ls, 0, sizeof(ls));
-      ls.base = (const double2 *)o.base;
+      ls.base = o.base;
       ls.bstride = o.bstride;
       ls.selmask = o.selmask;
       ls.count = 1u << T.rank();
       ls.lds_off = (uint32_t)(X.off[tid] / 16);
+      ls.slot = -1;
+      ls.f64 = 1;
+      const char *pb = (const char *)&ls;
+      blob.insert(blob.end(), pb, pb + sizeof(ls));
+    }
+    for (const Program::StagedGlobal &g : pr.staged_global) {
+      const Tensor &T = sch.tensors[g.tensor];
+      OpDesc o;
+      describe(g.tensor, o);
+      LeafStage ls;
+      std::memset(&ls, 0, sizeof(ls));
+      ls.base = o.base;
+      ls.bstride = o.bstride;
+      ls.sstride = o.sstride;
+      ls.E = o.E;
+      ls.ebstride = o.ebstride;
+      ls.esstride = o.esstride;
+      ls.count = 1u << T.rank();
+      ls.lds_off = (uint32_t)(g.off / 16);
+      ls.slot = (int16_t)g.slot;
+      ls.f64 = o.f64;
+      ls.global = 1;
       const char *pb = (const char *)&ls;
       blob.insert(blob.end(), pb, pb + sizeof(ls));
     }
     for (int st : pr.steps) {
       PStep ps = D->steps[st];
+      // operands staged from the workspace are read from the program's LDS
+      for (int i = 0; i < ps.nin; ++i)
+        for (const Program::StagedGlobal &g : pr.staged_global)
+          if (ps.in[i].loc == LOC_GLOBAL &&
+              ps.in[i].base == (const void *)(D->ws + sch.tensors[g.tensor].data_off)) {
+            ps.in[i].loc = LOC_LDS;
+            ps.in[i].off = (uint32_t)g.off;
+            ps.in[i].slot = (int16_t)g.slot;
+            ps.in[i].f64 = 1;
+          }
       bool lds_only = true;
       for (int i = 0; i < ps.nin; ++i) lds_only = lds_only && ps.in[i].loc == LOC_LDS;
       ps.wg_flags = lds_only ? 1u : 0u;
@@ -1415,7 +1477,7 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
                 ga.blob_off[j] = (uint32_t)D->blob_off[G.programs[k]];
                 ga.item_end[j] = (uint32_t)total;
                 ga.nsteps[j] = (uint16_t)pr.steps.size();
-                ga.nstage[j] = (uint16_t)pr.staged.size();
+                ga.nstage[j] = (uint16_t)(pr.staged.size() + pr.staged_global.size());
                 ga.bdep[j] = pr.bdep ? 1 : 0;
                 ga.sdep[j] = pr.sdep ? 1 : 0;
               }
