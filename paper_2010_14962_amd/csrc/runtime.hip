@@ -495,9 +495,22 @@ __device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32
 #undef QTN_WG
 }
 
+// Source of element i of a staging record for instance (b, sl, s).
+__device__ __forceinline__ double2 stage_load(const QTN_LDS LeafStage &L, uint32_t b, uint32_t sl,
+                                              uint32_t s, uint32_t i) {
+  if (L.global) {
+    const uint64_t o = (uint64_t)b * L.bstride + (uint64_t)sl * L.sstride + i;
+    if (L.f64) return ((const double2 *)L.base)[o];
+    const float2 f = ((const float2 *)L.base)[o];
+    return make_double2((double)f.x, (double)f.y);
+  }
+  return ((const double2 *)L.base)[b * L.bstride + (uint64_t)dpext(s, L.selmask) * L.count + i];
+}
+
 // Copies the staged tensors of a program into LDS for instance (b, sl, s).
-// Wave w takes records w, w+4, ...; eight loads are in flight before any
-// store.
+// Records of at most 64 values: wave w takes records w, w+4, ..., eight
+// loads in flight before any store.  Larger records: the whole workgroup,
+// eight loads in flight per thread.
 __device__ void stage_leaves(const QTN_LDS LeafStage *ls, uint32_t n, uint32_t b, uint32_t sl,
                              uint32_t s, QTN_LDS double *lds, QTN_LDS int *sE) {
   constexpr int G = 8;
@@ -512,36 +525,35 @@ __device__ void stage_leaves(const QTN_LDS LeafStage *ls, uint32_t n, uint32_t b
       const uint32_t j = j0 + r;
       if (j < n) {
         const QTN_LDS LeafStage &L = ls[j];
-        const uint32_t count = L.count, off = L.lds_off;
-        if (L.global) {
-          const uint64_t o = (uint64_t)b * L.bstride + (uint64_t)sl * L.sstride;
-          const bool f64 = L.f64 != 0;
-          const void *base = L.base;
-          auto load = [&](uint32_t i) -> double2 {
-            if (f64) return ((const double2 *)base)[o + i];
-            const float2 f = ((const float2 *)base)[o + i];
-            return make_double2((double)f.x, (double)f.y);
-          };
-          if (lane < count) {
-            v[r] = load(lane);
-            dst[r] = off + lane;
-          }
-          for (uint32_t i = lane + 64; i < count; i += 64) lds_st(lds, off + i, load(i));
-          if (lane == 0 && L.E) sE[L.slot] = L.E[b * L.ebstride + sl * L.esstride];
-        } else {
-          const double2 *src = (const double2 *)L.base + b * L.bstride +
-                               (uint64_t)dpext(s, L.selmask) * count;
-          if (lane < count) {
-            v[r] = src[lane];
-            dst[r] = off + lane;
-          }
-          for (uint32_t i = lane + 64; i < count; i += 64) lds_st(lds, off + i, src[i]);
+        const uint32_t count = L.count;
+        if (count <= 64 && lane < count) {
+          v[r] = stage_load(L, b, sl, s, lane);
+          dst[r] = L.lds_off + lane;
         }
+        if (lane == 0 && L.global && L.E) sE[L.slot] = L.E[b * L.ebstride + sl * L.esstride];
       }
     }
 #pragma unroll
     for (int r = 0; r < G; ++r)
       if (dst[r] != ~0u) lds_st(lds, dst[r], v[r]);
+  }
+  for (uint32_t j = 0; j < n; ++j) {
+    const QTN_LDS LeafStage &L = ls[j];
+    const uint32_t count = L.count;
+    if (count <= 64) continue;
+    for (uint32_t i0 = 0; i0 < count; i0 += G * 256) {
+      double2 v[G];
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const uint32_t i = i0 + r * 256 + threadIdx.x;
+        if (i < count) v[r] = stage_load(L, b, sl, s, i);
+      }
+#pragma unroll
+      for (int r = 0; r < G; ++r) {
+        const uint32_t i = i0 + r * 256 + threadIdx.x;
+        if (i < count) lds_st(lds, L.lds_off + i, v[r]);
+      }
+    }
   }
 }
 
