@@ -51,10 +51,13 @@ enum {
  * Precision forms.  QTN_FP64: every tensor complex128, FP64 arithmetic, no
  * rescaling.  QTN_FP32 (mixed): the large slice tensors, which carry the HBM
  * traffic, are stored as complex64 with a per-instance power-of-two exponent
- * (rescaled after every step); small tensors (under 3% of the bytes) and the
- * gate factors stay complex128; the streaming steps multiply in FP64
- * registers; dense steps use FP32 matrix cores.  QTN_3XBF16: as QTN_FP32 with
- * dense steps on split-BF16 matrix cores.  The slice sum is always FP64.
+ * (rescaled after every grid-wide step); small tensors (under 3% of the
+ * bytes), LDS-resident program tensors and the gate factors stay complex128;
+ * all products and sums run in FP64 registers.  The slice sum is always FP64.
+ * QTN_3XBF16 (split-BF16 matrix-core products) is reserved: the schedules
+ * built here sum at most 4 variables per step (Eq. (1) with |kappa| <= 4),
+ * an arithmetic intensity far below the matrix-core ridge, so no step is
+ * dense enough for it; qtn_plan rejects it with QTN_EINVAL.
  */
 enum { QTN_FP64 = 0, QTN_FP32 = 1, QTN_3XBF16 = 2 };
 

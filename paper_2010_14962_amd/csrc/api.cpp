@@ -58,6 +58,8 @@ extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
   if (p == 0 || p > 64) return fail(QTN_EINVAL, "p must be in [1, 64]");
   if (n_bitstrings == 0) return fail(QTN_EINVAL, "no bitstrings");
   if ((uint64_t)graph->n * p > 4096) return fail(QTN_EINVAL, "too many variables");
+  if (opts.precision == QTN_3XBF16)
+    return fail(QTN_EINVAL, "split-BF16 products need dense steps; no step of these schedules is dense");
   if (opts.precision < QTN_FP64 || opts.precision > QTN_3XBF16)
     return fail(QTN_EINVAL, "unknown precision");
   for (uint32_t l = 0; l < p; ++l)

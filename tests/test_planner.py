@@ -170,6 +170,9 @@ def test_errors_are_reported():
     with pytest.raises(QtnError):
         plan_instance(inst, cut_vars=[99])
     with pytest.raises(QtnError) as e:
+        plan_instance(inst, k=2, precision="3xbf16")
+    assert e.value.code == qtn.QTN_EINVAL and "dense" in str(e.value)
+    with pytest.raises(QtnError) as e:
         plan_instance(inst, k=-1, max_rank=0, k_max=0, cut_vars=None) and None
         plan_instance(inst, k=0, max_rank=1)
     assert e.value.code == qtn.QTN_ERANK
