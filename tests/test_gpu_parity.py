@@ -248,3 +248,30 @@ def test_step_timing_and_kernel_names():
     for st in timed:
         name = plan.step_kernel(st)
         assert name.startswith(("step_stream<true", "step_tiled<true")), name
+
+
+@pytest.mark.parametrize("mode", ["wide", "slice"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_n48_p2_grid_kernels_and_slices(mode, precision):
+    """n=48, p=2, k=3 (width 15): a schedule whose grid-wide steps take the
+    tiled, streaming and flat kernels; all slices summed and single slices
+    against the oracle."""
+    inst = make_instance(48, 2, 2, 12)
+    plan = plan_instance(inst, k=3, precision=precision, exec_mode=mode)
+    plan.bind_torch(8)
+    amps = _amps(plan, 0, 8)
+    cut, order = plan.cut(), plan.order()
+    for b in range(2):
+        ref = Q.ve_amplitude(48, inst.edges, 2, inst.gamma, inst.beta, inst.bitstrings[b])
+        assert _rel(amps[b], ref, 48) <= TOL[precision], b
+    scale = 2.0 ** -24
+    for s in (0, 5, 7):
+        part = _amps(plan, s, s + 1)
+        for b in range(2):
+            ref = Q.slice_partial(48, inst.edges, 2, inst.gamma, inst.beta, inst.bitstrings[b], cut, s,
+                                  order=order)
+            assert abs(part[b] - ref) <= TOL[precision] * max(abs(ref), scale), (s, b)
+    if mode == "wide":
+        kinds = {plan.step_kernel(st).split("<")[0] for st in range(plan.info()["n_steps"])} - {""}
+        print("kernels", sorted(kinds))
+        assert "step_tiled" in kinds or "step_stream" in kinds
