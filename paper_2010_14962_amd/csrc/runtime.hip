@@ -96,6 +96,8 @@ struct DeviceState {
   int mode = MODE_WIDE;
   void *leafbuf = nullptr;        // complex128 gate factors
   char *blobbuf = nullptr;        // program blobs
+  qtn_partial *host_partials = nullptr;      // pinned host memory, B partials
+  qtn_partial *host_partials_dev = nullptr;  // its device address
   std::vector<uint64_t> blob_off; // per program
   std::vector<uint64_t> leaf_elem_off;
   std::vector<PStep> steps;       // one descriptor per schedule step (host copy)
@@ -160,6 +162,7 @@ void device_state_free(DeviceState *d) {
   for (auto e : d->ev) (void)hipEventDestroy(e);
   for (void *p : {(void *)d->leafbuf, (void *)d->blobbuf})
     if (p) (void)hipFree(p);
+  if (d->host_partials) (void)hipHostFree(d->host_partials);
   delete d;
 }
 
@@ -983,7 +986,8 @@ template <bool SCALE>
 __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64, const int *E,
                                                  uint64_t bstride, uint64_t sstride,
                                                  uint32_t count, double pref,
-                                                 qtn_partial *partials, int init) {
+                                                 qtn_partial *partials, int init,
+                                                 qtn_partial *host_out) {
   __shared__ double sre[256], cre[256], sim[256], cim[256];
   const uint32_t b = blockIdx.x;
   const uint32_t t = threadIdx.x;
@@ -1042,7 +1046,10 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
       a.im_comp += w.im_comp + e2;
       a.im = s;
       partials[b] = a;
+      w = a;
     }
+    // the last wave also writes the result straight to pinned host memory
+    if (host_out) host_out[b] = w;
   }
 }
 
@@ -1161,6 +1168,10 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     double *lb = nullptr;
     if (int rc = upload(&lb, host, "hipMalloc(leaves)")) return rc;
     D->leafbuf = lb;
+    // pinned host memory the slice sum writes the final partials to
+    HIP_TRY(hipHostMalloc((void **)&D->host_partials, std::max<uint64_t>(P->net.B, 1) * sizeof(qtn_partial),
+                          hipHostMallocMapped));
+    HIP_TRY(hipHostGetDevicePointer((void **)&D->host_partials_dev, D->host_partials, 0));
   }
   if (lds_total > 64 * 1024) {
     HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<true>,
@@ -1471,7 +1482,8 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
           hipLaunchKernelGGL((slice_sum<SCALE>), dim3((unsigned)B), dim3(256), 0, stream,
                              (const void *)(D->ws + res.data_off), res.f64 ? 1u : 0u,
                              (const int *)(D->ws + res.exp_off), rb, rs, (uint32_t)cnt,
-                             P->net.prefactor, partials, first ? 1 : 0);
+                             P->net.prefactor, partials, first ? 1 : 0,
+                             s_lo + S >= hi ? D->host_partials_dev : (qtn_partial *)nullptr);
           first = false;
         } else {
           const size_t g = (size_t)(u - 1);
@@ -1641,9 +1653,8 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
     HIP_TRY(hipEventRecord(D->gdep, stream));
     HIP_TRY(hipStreamWaitEvent(D->gstream, D->gdep, 0));
     HIP_TRY(hipGraphLaunch(D->gexec, D->gstream));
-    HIP_TRY(hipMemcpyAsync(out, D->ws + D->L.partial_off, B * sizeof(qtn_partial),
-                           hipMemcpyDeviceToHost, D->gstream));
     HIP_TRY(hipStreamSynchronize(D->gstream));
+    std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
     D->ev_used = D->g_ev_used;
     D->ev_bytes = D->g_ev_bytes;
     D->ev_flops = D->g_ev_flops;
@@ -1651,9 +1662,8 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
   } else {
     int rc = enqueue(stream);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(out, D->ws + D->L.partial_off, B * sizeof(qtn_partial),
-                           hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
   }
   if (D->timing) {
     for (size_t j = 0; j + 1 < D->ev_used; j += 2) {
