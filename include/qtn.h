@@ -207,10 +207,12 @@ int qtn_contract(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi,
 /*
  * Enables (1, the default after binding) or disables (0) replay of captured
  * HIP graphs.  With graphs, the launch sequence of a slice range is captured
- * on the first qtn_contract for that range, on a library stream that waits
- * for `stream`, and replayed by later calls with the same range; the
- * sequence contains no memset nodes.  With graphs off, kernels are launched
- * on `stream` directly.  Requires a bound workspace.
+ * on the first qtn_contract for that range (on a library stream, so nothing
+ * runs during capture) and replayed on `stream` by that and later calls with
+ * the same range; the sequence contains no memset nodes.  With graphs off,
+ * kernels are launched on `stream` directly.  Either way independent
+ * launches may run on library side streams that are joined back into
+ * `stream` before the call returns.  Requires a bound workspace.
  */
 int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
 

@@ -883,7 +883,9 @@ LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, 
       r.push_back({T.exp_off, T.exp_off + e, w});
     }
   };
-  if (scaled && L.exp_bytes) rng[0].push_back({L.data_bytes, L.data_bytes + L.exp_bytes, true});
+  // Unit 0 launches nothing: the exponent region is cleared once when the
+  // workspace is bound and then by the slice sum at the end of every wave,
+  // for the next one (its words are read by nobody after the slice sum).
   for (size_t g = 0; g < nl; ++g) {
     const LaunchGroup &G = x.launches[g];
     std::vector<int> sts;
@@ -904,6 +906,7 @@ LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, 
   }
   data(s.result, false, rng[nl + 1]);
   rng[nl + 1].push_back({L.partial_off, L.partial_off + B * 32, true});
+  if (scaled && L.exp_bytes) rng[nl + 1].push_back({L.data_bytes, L.data_bytes + L.exp_bytes, true});
 
   auto conflict = [&](size_t a, size_t b) {
     for (const Range &p : rng[a])

@@ -134,7 +134,6 @@ struct DeviceState {
   // captured launch sequence of one slice range, replayed while it matches
   bool use_graphs = true;
   hipStream_t gstream = nullptr;
-  hipEvent_t gdep = nullptr;
   hipGraphExec_t gexec = nullptr;
   uint64_t g_lo = 0, g_hi = 0;
   bool g_timing = false;
@@ -151,7 +150,6 @@ static void drop_graph(DeviceState *d) {
 void device_state_free(DeviceState *d) {
   if (!d) return;
   drop_graph(d);
-  if (d->gdep) (void)hipEventDestroy(d->gdep);
   if (d->gstream) (void)hipStreamDestroy(d->gstream);
   for (auto e : d->unit_ev) (void)hipEventDestroy(e);
   if (d->fork_ev) (void)hipEventDestroy(d->fork_ev);
@@ -987,7 +985,8 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
                                                  uint64_t bstride, uint64_t sstride,
                                                  uint32_t count, double pref,
                                                  qtn_partial *partials, int init,
-                                                 qtn_partial *host_out) {
+                                                 qtn_partial *host_out, uint32_t *clear,
+                                                 uint64_t nclear, uint64_t keep_lo, uint64_t keep_hi) {
   __shared__ double sre[256], cre[256], sim[256], cim[256];
   const uint32_t b = blockIdx.x;
   const uint32_t t = threadIdx.x;
@@ -1051,12 +1050,12 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
     // the last wave also writes the result straight to pinned host memory
     if (host_out) host_out[b] = w;
   }
-}
-
-__global__ void zero_words(uint32_t *p, uint64_t n) {
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
+  // Clear the exponent words for the next wave, except the result's
+  // exponents [keep_lo, keep_hi) that this kernel reads; every other word
+  // has been read by its consumer, all of which ran before this launch.
+  if (clear)
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + t; i < nclear; i += (uint64_t)gridDim.x * blockDim.x)
+      if (i < keep_lo || i >= keep_hi) clear[i] = 0u;
 }
 
 // ---------------------------------------------------------------------------
@@ -1205,6 +1204,8 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   D->mode = mode;
   D->ws = (char *)dev_ptr;
   D->ws_bytes = bytes;
+  // the exponent words start cleared; the slice sum clears them after each wave
+  if (P->precision != QTN_FP64 && L.exp_bytes) HIP_TRY(hipMemset(D->ws + L.data_bytes, 0, L.exp_bytes));
   D->L = L;
   D->max_slots = max_slots;
   D->lds_bytes = lds_bytes;
@@ -1472,18 +1473,17 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
       {
         const hipStream_t stream = ustream;
         if (u == 0) {
-          if (SCALE && D->L.exp_bytes) {
-            const uint64_t words = D->L.exp_bytes / 4;
-            hipLaunchKernelGGL(zero_words, dim3((unsigned)std::min<uint64_t>((words + 255) / 256, 4096)),
-                               dim3(256), 0, stream, (uint32_t *)(D->ws + D->L.data_bytes), words);
-          }
+          // exponents were cleared at bind time or by the previous slice sum
         } else if (u == U - 1) {
           const uint64_t rb = res.bdep ? (res.sdep ? S : 1) : 0, rs = res.sdep ? 1 : 0;
           hipLaunchKernelGGL((slice_sum<SCALE>), dim3((unsigned)B), dim3(256), 0, stream,
                              (const void *)(D->ws + res.data_off), res.f64 ? 1u : 0u,
                              (const int *)(D->ws + res.exp_off), rb, rs, (uint32_t)cnt,
                              P->net.prefactor, partials, first ? 1 : 0,
-                             s_lo + S >= hi ? D->host_partials_dev : (qtn_partial *)nullptr);
+                             s_lo + S >= hi ? D->host_partials_dev : (qtn_partial *)nullptr,
+                             (SCALE && D->L.exp_bytes) ? (uint32_t *)(D->ws + D->L.data_bytes) : (uint32_t *)nullptr,
+                             D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
+                             SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0);
           first = false;
         } else {
           const size_t g = (size_t)(u - 1);
@@ -1616,10 +1616,9 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
   };
   if (D->use_graphs) {
     // The launch sequence of [lo, hi) is captured once on an internal stream
-    // (ordered after the caller's stream) and replayed while it matches.
+    // and replayed on the caller's stream while it matches.
     if (!D->gstream) {
       HIP_TRY(hipStreamCreateWithFlags(&D->gstream, hipStreamNonBlocking));
-      HIP_TRY(hipEventCreateWithFlags(&D->gdep, hipEventDisableTiming));
     }
     if (!D->gexec || D->g_lo != lo || D->g_hi != hi || D->g_timing != D->timing) {
       drop_graph(D);
@@ -1650,10 +1649,9 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
       D->g_ev_flops = D->ev_flops;
       D->g_ev_step = D->ev_step;
     }
-    HIP_TRY(hipEventRecord(D->gdep, stream));
-    HIP_TRY(hipStreamWaitEvent(D->gstream, D->gdep, 0));
-    HIP_TRY(hipGraphLaunch(D->gexec, D->gstream));
-    HIP_TRY(hipStreamSynchronize(D->gstream));
+    // the replay is ordered on the caller's stream itself
+    HIP_TRY(hipGraphLaunch(D->gexec, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
     std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
     D->ev_used = D->g_ev_used;
     D->ev_bytes = D->g_ev_bytes;
