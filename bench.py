@@ -3,10 +3,14 @@
 Workload (default): random 3-regular graph, n = 120 qubits, QAOA depth 1,
 8 output bitstrings batched, cut size k = the smallest k whose searched cut
 keeps every slice tensor at rank <= 26; seeded synthetic instance.  One step
-is one qtn_contract over all 2^k slices of all 8 bitstrings (the whole hot
-path: slice set-up, every contraction step, the FP64 slice sum).  The mixed
-form (FP32 storage and arithmetic with per-slice power-of-two rescaling) is
-the headline; the plain FP64 GPU contraction is timed beside it.
+is one contraction over all 2^k slices of all 8 bitstrings (the whole hot
+path: slice set-up, every contraction step, the FP64 slice sum, the partials
+in host memory), one synchronous qtn_contract (graph replay) per step.  The
+same steps enqueued back to back with qtn_contract_async are timed as
+well.  The mixed form (complex64 storage
+of the large tensors with per-instance power-of-two rescaling, FP64
+arithmetic) is the headline; the plain FP64 GPU contraction is timed beside
+it.
 
 Prints one JSON line.  Single GPU only.
 """
@@ -17,6 +21,8 @@ import multiprocessing as mp
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -165,6 +171,24 @@ def main():
     print("# workload %s k=%d width=%d steps=%d B=%d S=%d plan %.3fs" %
           (args.workload, k, info["width"], info["n_steps"], B, S, plan_s), file=sys.stderr, flush=True)
 
+    def run_pipelined(plan, steps, warmup):
+        """Timed region: `steps` asynchronous contractions enqueued back to
+        back on the stream (graph replays), each copying its partials to its
+        own slot of a pinned host buffer, then one synchronisation."""
+        plan.set_graphs(True)
+        buf = torch.zeros((steps + warmup, B, 4), dtype=torch.float64).pin_memory()
+        for i in range(warmup):
+            plan.contract_async(0, nsl, buf[i].data_ptr(), stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(steps):
+            plan.contract_async(0, nsl, buf[warmup + i].data_ptr(), stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        last = buf[warmup + steps - 1].numpy()
+        assert all(np.array_equal(buf[warmup + i].numpy(), last) for i in range(steps))
+        return el, [complex(r[0] + r[2], r[1] + r[3]) for r in last]
+
     def run(plan, steps, warmup, timing):
         """Timed region: `steps` contractions bracketed by device syncs.  With
         `timing`, kernels are launched directly (no graph replay) and each
@@ -188,9 +212,13 @@ def main():
         plan.set_graphs(True)
         return el, [p.value() for p in out], tm
 
-    # value: replayed graphs, nothing else in the timed region
+    # value: one synchronous qtn_contract per step (graph replay), nothing
+    # else in the timed region
     el, amps, _ = run(mixed, args.steps, args.warmup, False)
-    print("# mixed: %.3f ms/step" % (1e3 * el / args.steps), file=sys.stderr, flush=True)
+    print("# mixed, synchronous calls: %.3f ms/step" % (1e3 * el / args.steps), file=sys.stderr, flush=True)
+    # the same steps enqueued back to back with qtn_contract_async
+    el_pipe, _ = run_pipelined(mixed, args.steps, args.warmup)
+    print("# mixed, pipelined: %.3f ms/step" % (1e3 * el_pipe / args.steps), file=sys.stderr, flush=True)
     # roofline: same contraction, direct launches with per-launch events
     el_t, _, tm = run(mixed, args.steps, 1, True)
     print("# mixed, direct launches with events: %.3f ms/step; %s" %
@@ -245,6 +273,8 @@ def main():
                    "seed": args.seed, "slices_per_wave": S, "graph": "random 3-regular",
                    "precision": "fp32 + per-slice power-of-two rescale, fp64 slice sum"},
         "slices_per_sec": slices_per_s,
+        "timing": "one synchronous qtn_contract per step (graph replay, partials in host memory)",
+        "pipelined_ms_per_step": 1e3 * el_pipe / args.steps,
         "fp64": {"amplitudes_per_sec": B * n64 / el64, "slices_per_sec": B * nsl * n64 / el64,
                  "ms_per_step": 1e3 * el64 / n64},
         "mixed_over_fp64": (amps_per_s / (B * n64 / el64)),

@@ -205,6 +205,18 @@ int qtn_contract(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi,
                  void *stream, qtn_partial *out);
 
 /*
+ * As qtn_contract, but returns once the work is enqueued: the contraction and
+ * a copy of the partials to `out` are ordered on `stream`, and `out` is valid
+ * after the caller synchronises the stream.  Pinned host memory for `out`
+ * keeps the copy asynchronous.  Calls on one plan share its workspace: issue
+ * them on one stream (they then run one after another) or synchronise in
+ * between.  lo == hi writes exact zeros to `out` at once.  Not with timing on
+ * (QTN_ESTATE).  For serving loops that pipeline many contractions.
+ */
+int qtn_contract_async(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi, void *stream,
+                       qtn_partial *out);
+
+/*
  * Enables (1, the default after binding) or disables (0) replay of captured
  * HIP graphs.  With graphs, the launch sequence of a slice range is captured
  * on the first qtn_contract for that range (on a library stream, so nothing

@@ -1568,8 +1568,8 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
   return QTN_OK;
 }
 
-extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v,
-                            qtn_partial *out) {
+static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v,
+                         qtn_partial *out, bool async) {
   set_error("");
   if (!P || !out) {
     set_error("NULL argument");
@@ -1597,6 +1597,10 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
   }
   hipStream_t stream = (hipStream_t)stream_v;
   DeviceState *D = P->dev;
+  if (async && D->timing) {
+    set_error("timing reads its events when the call returns; use qtn_contract");
+    return QTN_ESTATE;
+  }
   if (D->timing) {
     // events are created before any capture begins: two per timed launch
     const ExecPlan &X = P->exec[D->mode];
@@ -1651,8 +1655,13 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
     }
     // the replay is ordered on the caller's stream itself
     HIP_TRY(hipGraphLaunch(D->gexec, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
+    if (async) {
+      HIP_TRY(hipMemcpyAsync(out, D->ws + D->L.partial_off, B * sizeof(qtn_partial),
+                             hipMemcpyDeviceToHost, stream));
+    } else {
+      HIP_TRY(hipStreamSynchronize(stream));
+      std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
+    }
     D->ev_used = D->g_ev_used;
     D->ev_bytes = D->g_ev_bytes;
     D->ev_flops = D->g_ev_flops;
@@ -1660,8 +1669,13 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
   } else {
     int rc = enqueue(stream);
     if (rc) return rc;
-    HIP_TRY(hipStreamSynchronize(stream));
-    std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
+    if (async) {
+      HIP_TRY(hipMemcpyAsync(out, D->ws + D->L.partial_off, B * sizeof(qtn_partial),
+                             hipMemcpyDeviceToHost, stream));
+    } else {
+      HIP_TRY(hipStreamSynchronize(stream));
+      std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
+    }
   }
   if (D->timing) {
     for (size_t j = 0; j + 1 < D->ev_used; j += 2) {
@@ -1691,6 +1705,16 @@ extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *strea
   D->ev_flops.clear();
   D->ev_step.clear();
   return QTN_OK;
+}
+
+extern "C" int qtn_contract(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream,
+                            qtn_partial *out) {
+  return contract_impl(P, lo, hi, stream, out, false);
+}
+
+extern "C" int qtn_contract_async(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream,
+                                  qtn_partial *out) {
+  return contract_impl(P, lo, hi, stream, out, true);
 }
 
 extern "C" int qtn_plan_set_graphs(qtn_plan_t *P, int enable) {

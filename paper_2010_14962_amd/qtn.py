@@ -79,7 +79,7 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_cost_features", "qtn_cost_exact", "qtn_mlp_create", "qtn_mlp_destroy",
            "qtn_mlp_num_params", "qtn_mlp_get_params", "qtn_mlp_set_params", "qtn_mlp_get_grads",
            "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search",
-           "qtn_plan_step_timing", "qtn_plan_step_kernel"]
+           "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_contract_async"]
 COST_FEATURES = 32
 
 
@@ -112,6 +112,7 @@ def lib():
     L.qtn_plan_workspace_bytes.argtypes = [c_void_p, c_uint64, POINTER(c_uint64)]
     L.qtn_plan_bind_workspace.argtypes = [c_void_p, c_void_p, c_uint64, c_uint64]
     L.qtn_contract.argtypes = [c_void_p, c_uint64, c_uint64, c_void_p, POINTER(QtnPartial)]
+    L.qtn_contract_async.argtypes = [c_void_p, c_uint64, c_uint64, c_void_p, c_void_p]
     L.qtn_partial_combine.argtypes = [POINTER(QtnPartial), POINTER(QtnPartial), POINTER(QtnPartial)]
     L.qtn_plan_set_timing.argtypes = [c_void_p, c_int32]
     L.qtn_plan_set_graphs.argtypes = [c_void_p, c_int32]
@@ -263,6 +264,14 @@ class Plan:
         buf = ctypes.create_string_buffer(128)
         _check(lib().qtn_plan_step_kernel(self._h, step, buf, len(buf)))
         return buf.value.decode()
+
+    def contract_async(self, slice_lo: int, slice_hi: int, out_ptr: int,
+                       stream: Optional[int] = None) -> None:
+        """Enqueues the contraction and the copy of the partials to the host
+        address out_ptr (n_bitstrings x 4 doubles; pinned memory keeps it
+        asynchronous); valid after the stream is synchronised."""
+        _check(lib().qtn_contract_async(self._h, slice_lo, slice_hi, c_void_p(stream or 0),
+                                        c_void_p(out_ptr)))
 
     def contract(self, slice_lo: int, slice_hi: int, stream: Optional[int] = None) -> List[QtnPartial]:
         out = (QtnPartial * self.n_bitstrings)()

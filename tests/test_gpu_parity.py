@@ -275,3 +275,25 @@ def test_n48_p2_grid_kernels_and_slices(mode, precision):
         kinds = {plan.step_kernel(st).split("<")[0] for st in range(plan.info()["n_steps"])} - {""}
         print("kernels", sorted(kinds))
         assert "step_tiled" in kinds or "step_stream" in kinds
+
+
+@pytest.mark.parametrize("graphs", [True, False])
+def test_async_pipelined_contractions_match_sync(graphs):
+    """Several asynchronous contractions enqueued back to back on one stream,
+    each copying its partials to its own slot of a pinned buffer, give the
+    synchronous partials bit for bit."""
+    inst = workload_instance("qaoa_n40_p2_b32_k8", seed=3)
+    plan = plan_instance(inst, k=8, precision="fp32")
+    plan.bind_torch(64)
+    plan.set_graphs(graphs)
+    ref = np.array([[p.re, p.im, p.re_comp, p.im_comp] for p in plan.contract(0, 256, _stream())])
+    K = 4
+    buf = torch.zeros((K, 32, 4), dtype=torch.float64).pin_memory()
+    for i in range(K):
+        plan.contract_async(0, 256, buf[i].data_ptr(), _stream())
+    torch.cuda.synchronize()
+    for i in range(K):
+        assert np.array_equal(buf[i].numpy(), ref), i
+    part = np.zeros((32, 4))
+    plan.contract_async(5, 5, part.ctypes.data, _stream())
+    assert not part.any()
