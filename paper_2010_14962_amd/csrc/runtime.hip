@@ -734,14 +734,18 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
     uint32_t wmax = 0;
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
       const uint32_t j0 = u * jspan;            // in units of 256 elements
-      const uint32_t ch = j0 >> 4;
       uint32_t hoff[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) hoff[v] = dpext(ch, hmask[v]) << hshift[v];
 #pragma unroll 1
       for (uint32_t jj = 0; jj < jspan; ++jj) {
         const uint32_t j = (j0 + jj) & 15u;
         const uint32_t c = ((j0 + jj) << 8) | t;
+        if (jj == 0 || j == 0) {
+          // a unit may span several chunks of 16 rows: the high part of
+          // each operand index changes at every chunk boundary
+          const uint32_t ch = (j0 + jj) >> 4;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) hoff[v] = dpext(ch, hmask[v]) << hshift[v];
+        }
         double2 acc = make_double2(0.0, 0.0);
         // all loads of a group of kappa values are issued before any product
         constexpr uint32_t KU = NKAP > 4 ? 4 : NKAP;
@@ -1531,12 +1535,15 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
               HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
             }
             if (streaming) {
-              // units of jspan x 256 elements: about 2048 blocks over the chip
+              // units of jspan x 256 elements: about 1024 blocks over the chip
+              // (4 per compute unit), each walking up to 32 rows, so that the
+              // per-block set-up is paid once per 8192 outputs; measured on
+              // the n=120 step, 2048 and 512 blocks are slower
               const uint32_t rows = (1u << d.rC) >> 8;
-              uint32_t jspan = 16;
-              while (jspan > 1 && (uint64_t)(rows / jspan) * Q < 2048) jspan >>= 1;
+              uint32_t jspan = 32;
+              while (jspan > 1 && (uint64_t)(rows / jspan) * Q < 1024) jspan >>= 1;
               const uint64_t units = rows / jspan;
-              const uint64_t want = std::max<uint64_t>(1, 4096 / std::max<uint64_t>(Q, 1));
+              const uint64_t want = std::max<uint64_t>(1, 2048 / std::max<uint64_t>(Q, 1));
               const dim3 grid((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
               launch_stream<SCALE>(d, grid, stream, nb, ns, s_lo, jspan);
             } else {
