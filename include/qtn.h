@@ -44,7 +44,8 @@ enum {
   QTN_ERANK = -3,  /* no cut set of size <= k_max meets max_rank          */
   QTN_ENOMEM = -4, /* workspace missing or too small; host allocation     */
   QTN_EHIP = -5,   /* HIP runtime error (message names the call)         */
-  QTN_ESTATE = -6  /* call not valid in the plan's current state          */
+  QTN_ESTATE = -6, /* call not valid in the plan's current state         */
+  QTN_ETIMEOUT = -7 /* qtn_contract's wait exceeded QTN_SYNC_TIMEOUT_S      */
 };
 
 /*
@@ -199,7 +200,10 @@ int qtn_plan_bind_workspace(qtn_plan_t *plan, void *device_ptr, uint64_t bytes,
  * (a hipStream_t; NULL = default stream) and writes one compensated partial
  * sum per bitstring to out[0..n_bitstrings).  Eq. (2): summing the partials of
  * disjoint ranges that cover [0, 2^k) gives the amplitude.  The call waits for
- * the stream before returning.  lo == hi gives exact zeros.
+ * the stream before returning.  lo == hi gives exact zeros.  With the
+ * environment variable QTN_SYNC_TIMEOUT_S set to a positive number of seconds
+ * (read once per process), that wait gives up after so long with QTN_ETIMEOUT
+ * and leaves the work in flight; by default it waits without limit.
  */
 int qtn_contract(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi,
                  void *stream, qtn_partial *out);
@@ -222,9 +226,10 @@ int qtn_contract_async(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi, v
  * on the first qtn_contract for that range (on a library stream, so nothing
  * runs during capture) and replayed on `stream` by that and later calls with
  * the same range; the sequence contains no memset nodes.  With graphs off,
- * kernels are launched on `stream` directly.  Either way independent
- * launches may run on library side streams that are joined back into
- * `stream` before the call returns.  Requires a bound workspace.
+ * kernels are launched on `stream` directly, one after another in
+ * the plan's enqueue order.  Inside a captured graph, independent launches
+ * sit on parallel branches (captured from library side streams joined back
+ * before the capture ends).  Requires a bound workspace.
  */
 int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
 

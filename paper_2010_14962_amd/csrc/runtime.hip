@@ -9,11 +9,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/qtn.h"
@@ -1076,6 +1078,37 @@ static int hip_fail(hipError_t e, const char *what) {
     if (_e != hipSuccess) return hip_fail(_e, #call); \
   } while (0)
 
+// Waits for `stream` to drain.  With QTN_SYNC_TIMEOUT_S set to a positive
+// number of seconds (read once), the wait polls the stream and gives up with
+// QTN_ETIMEOUT after that long, so that work that never completes becomes an
+// error naming the call instead of a process that blocks for ever; the work
+// itself is left in flight.  Unset or 0: hipStreamSynchronize.
+static int wait_stream(hipStream_t stream, const char *what) {
+  static const double limit = [] {
+    const char *e = std::getenv("QTN_SYNC_TIMEOUT_S");
+    return e ? std::atof(e) : 0.0;
+  }();
+  if (!(limit > 0)) {
+    const hipError_t e = hipStreamSynchronize(stream);
+    return e == hipSuccess ? QTN_OK : hip_fail(e, what);
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint32_t i = 1;; ++i) {
+    const hipError_t q = hipStreamQuery(stream);
+    if (q == hipSuccess) return QTN_OK;
+    if (q != hipErrorNotReady) return hip_fail(q, what);
+    if ((i & 63u) == 0) {
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (el > limit) {
+        set_error(std::string(what) + ": stream work unfinished after " + std::to_string(limit) +
+                  " s (QTN_SYNC_TIMEOUT_S)");
+        return QTN_ETIMEOUT;
+      }
+      std::this_thread::yield();
+    }
+  }
+}
+
 template <typename T>
 static int upload(T **dst, const std::vector<T> &src, const char *what) {
   if (*dst) (void)hipFree(*dst);
@@ -1444,7 +1477,7 @@ static void launch_stream(const PStep &d, dim3 grid, hipStream_t stream, uint32_
 }
 
 template <bool SCALE>
-static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream) {
+static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream, bool concurrent) {
   DeviceState *D = P->dev;
   const Schedule &sch = P->sched;
   const ExecPlan &X = P->exec[D->mode];
@@ -1455,7 +1488,10 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
   const uint64_t scratch_stride = (X.scratch_per_wg + 255) & ~uint64_t(255);
   bool first = true;
   const LaunchGraph &lg = D->lg;
-  const bool multi = lg.nstreams > 1 && !D->timing;
+  // Side streams are used only while a graph is being captured: the graph
+  // then holds the launch graph's edges.  Direct launches, and any launch
+  // sequence with timing on, run on `stream` in the enqueue order.
+  const bool multi = concurrent && lg.nstreams > 1 && !D->timing;
   auto unit_stream = [&](int u) {
     return (!multi || lg.stream[u] == 0) ? stream : D->side[lg.stream[u] - 1];
   };
@@ -1622,8 +1658,9 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
       D->ev.push_back(e);
     }
   }
-  auto enqueue = [&](hipStream_t st) {
-    return P->precision == QTN_FP64 ? run_waves<false>(P, lo, hi, st) : run_waves<true>(P, lo, hi, st);
+  auto enqueue = [&](hipStream_t st, bool concurrent) {
+    return P->precision == QTN_FP64 ? run_waves<false>(P, lo, hi, st, concurrent)
+                                    : run_waves<true>(P, lo, hi, st, concurrent);
   };
   if (D->use_graphs) {
     // The launch sequence of [lo, hi) is captured once on an internal stream
@@ -1639,7 +1676,7 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
       D->ev_step.clear();
       hipGraph_t graph = nullptr;
       HIP_TRY(hipStreamBeginCapture(D->gstream, hipStreamCaptureModeThreadLocal));
-      int rc = enqueue(D->gstream);
+      int rc = enqueue(D->gstream, true);
       hipError_t ce = hipStreamEndCapture(D->gstream, &graph);
       if (rc) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -1666,7 +1703,7 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
       HIP_TRY(hipMemcpyAsync(out, D->ws + D->L.partial_off, B * sizeof(qtn_partial),
                              hipMemcpyDeviceToHost, stream));
     } else {
-      HIP_TRY(hipStreamSynchronize(stream));
+      if (int rc = wait_stream(stream, "qtn_contract")) return rc;
       std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
     }
     D->ev_used = D->g_ev_used;
@@ -1674,13 +1711,13 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
     D->ev_flops = D->g_ev_flops;
     D->ev_step = D->g_ev_step;
   } else {
-    int rc = enqueue(stream);
+    int rc = enqueue(stream, false);
     if (rc) return rc;
     if (async) {
       HIP_TRY(hipMemcpyAsync(out, D->ws + D->L.partial_off, B * sizeof(qtn_partial),
                              hipMemcpyDeviceToHost, stream));
     } else {
-      HIP_TRY(hipStreamSynchronize(stream));
+      if (int rc = wait_stream(stream, "qtn_contract")) return rc;
       std::memcpy(out, D->host_partials, B * sizeof(qtn_partial));
     }
   }

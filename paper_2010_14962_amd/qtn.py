@@ -18,7 +18,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqtn.so")
 
-QTN_OK, QTN_EINVAL, QTN_ERANGE, QTN_ERANK, QTN_ENOMEM, QTN_EHIP, QTN_ESTATE = 0, -1, -2, -3, -4, -5, -6
+QTN_OK, QTN_EINVAL, QTN_ERANGE, QTN_ERANK, QTN_ENOMEM, QTN_EHIP, QTN_ESTATE, QTN_ETIMEOUT = \
+    0, -1, -2, -3, -4, -5, -6, -7
 QTN_FP64, QTN_FP32, QTN_3XBF16 = 0, 1, 2
 PRECISIONS = {"fp64": QTN_FP64, "fp32": QTN_FP32, "3xbf16": QTN_3XBF16}
 STEP_REC, TENSOR_REC = 24, 40
