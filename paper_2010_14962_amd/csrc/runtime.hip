@@ -858,28 +858,39 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
     const int sh = I.sh;
     uint32_t wmax = 0;
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+      // operand bases of the current chunk of 16 rows: instance offset plus
+      // the index part of the row bits above the lowest four
+      const char *cbase[NV];
 #pragma unroll 1
       for (uint32_t jj = 0; jj < jspan; ++jj) {
         const uint32_t row = u * jspan + jj;
+        if (jj == 0 || (row & 15u) == 0) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v)
+            cbase[v] = (const char *)d.in[v].base +
+                       (I.off[v] + ((uint64_t)dpext(row >> 4, hmask[v]) << hshift[v])) * (v < NF ? 8u : 16u);
+        }
         __syncthreads();  // the previous row's readers are done
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const OpDesc &in = d.in[v];
-          const uint64_t rb = I.off[v] + s_mid[v][row & 15u] +
-                              ((uint64_t)dpext(row >> 4, hmask[v]) << hshift[v]);
+          constexpr uint32_t esz_f = 8u, esz_d = 16u;
+          const uint32_t esz = v < NF ? esz_f : esz_d;
+          // the table entry is the same for every lane
+          const char *rb = cbase[v] + (uint64_t)__builtin_amdgcn_readfirstlane(s_mid[v][row & 15u]) * esz;
           const uint32_t n = 1u << (nkv[v] + nlo[v]);
           const uint32_t lmask = (1u << nlo[v]) - 1u;
           if (v == fold) {
             // complex128 copy times the kappa coefficient of its run
             QTN_LDS lds_c128 *dst = (QTN_LDS lds_c128 *)(stage + soff[v]);
             for (uint32_t e = t; e < n; e += 256) {
-              const uint64_t g = rb + ((uint64_t)(e >> nlo[v]) << pc[v]) + (e & lmask);
+              // byte offset within the operand: below 2^31 (checked by the host)
+              const uint32_t g = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
               double2 x;
               if (v < NF) {
-                const float2 f = ((const float2 *)in.base)[g];
+                const float2 f = *(const float2 *)(rb + g);
                 x = make_double2((double)f.x, (double)f.y);
               } else {
-                x = ((const double2 *)in.base)[g];
+                x = *(const double2 *)(rb + g);
               }
               x = cmul(x, s_coef[e >> nlo[v]]);
               lds_c128 c;
@@ -889,11 +900,11 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
             }
           } else {
             for (uint32_t e = t; e < n; e += 256) {
-              const uint64_t g = rb + ((uint64_t)(e >> nlo[v]) << pc[v]) + (e & lmask);
+              const uint32_t g = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
               if (v < NF)
-                ((float2 *)(stage + soff[v]))[e] = ((const float2 *)in.base)[g];
+                ((float2 *)(stage + soff[v]))[e] = *(const float2 *)(rb + g);
               else
-                ((double2 *)(stage + soff[v]))[e] = ((const double2 *)in.base)[g];
+                ((double2 *)(stage + soff[v]))[e] = *(const double2 *)(rb + g);
             }
           }
         }
@@ -1419,6 +1430,8 @@ static uint32_t tiled_lds_bytes(const PStep &d) {
     const uint32_t cb = d.rC >= 32 ? ~0u : ((1u << d.rC) - 1u);
     const uint64_t n = 1ull << (__builtin_popcount(d.rC >= 32 ? 0u : (in.mask >> d.rC)) +
                                 __builtin_popcount(in.mask & cb & 255u));
+    // byte offsets within one operand instance are computed in 32 bits
+    if ((uint64_t)(v < d.nf32 ? 8u : 16u) << __builtin_popcount(in.mask) >= (1ull << 31)) return 0;
     staged += n;
     bytes += n * (v < d.nf32 && v != d.tiled_fold ? 8u : 16u);
   }
