@@ -188,6 +188,15 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return r;
 }
 
+// c + a b with four fused multiply-adds
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
+  c.x = fma(a.x, b.x, c.x);
+  c.x = fma(-a.y, b.y, c.x);
+  c.y = fma(a.x, b.y, c.y);
+  c.y = fma(a.y, b.x, c.y);
+  return c;
+}
+
 __device__ __forceinline__ double2 load_g(const void *base, uint32_t f64, uint64_t i) {
   if (f64) return ((const double2 *)base)[i];
   const float2 f = ((const float2 *)base)[i];
@@ -815,14 +824,27 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
   extern __shared__ __align__(16) char stage[];
   __shared__ uint32_t s_mid[NV][16];
   __shared__ uint32_t s_kap[NV][NKAP];
-  __shared__ double2 s_coef[NKAP];
+  __shared__ double2 s_coef[NKAP];   // by kappa
+  __shared__ double2 s_coefl[NKAP];  // by position in the sum (unfolded steps)
   __shared__ uint32_t red4[4];
   const uint32_t t = threadIdx.x;
   const uint32_t cb = out_bits(d.rC);
+  // The kappa sum runs in a permuted order: when the last operand does not
+  // depend on some summed bit b, bits 0 and b trade places, so that the
+  // positions 2j and 2j+1 share that operand's element and the products of
+  // the other operands are summed before it multiplies them once (the same
+  // sum, regrouped by distributivity).  The swap is its own inverse.
+  const uint32_t missing = NV > 1 ? ~(d.in[NV - 1].mask >> d.rC) & (NKAP - 1u) : 0u;
+  const bool fact = missing != 0;
+  const uint32_t bsw = fact ? (uint32_t)__builtin_ctz(missing) : 0u;
+  auto perm = [&](uint32_t k) {
+    const uint32_t x = (k ^ (k >> bsw)) & 1u;  // bits 0 and bsw differ
+    return k ^ (x | (x << bsw));
+  };
   if (t < NV * 16) s_mid[t >> 4][t & 15] = dpext((t & 15) << 8, d.in[t >> 4].mask & cb);
   if (t < NV * NKAP) {
     const OpDesc &in = d.in[t / NKAP];
-    s_kap[t / NKAP][t % NKAP] = dpext(t % NKAP, in.mask >> d.rC) << __popc(in.mask & cb & 255u);
+    s_kap[t / NKAP][t % NKAP] = dpext(perm(t % NKAP), in.mask >> d.rC) << __popc(in.mask & cb & 255u);
   }
   uint32_t lo[NV], soff[NV], nlo[NV], nkv[NV], pc[NV], hmask[NV], hshift[NV];
   uint32_t bytes = 0;
@@ -852,11 +874,44 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
       for (int i = NV; i < kMaxIn; ++i)
         if (i < d.nin) c = cmul(c, load_g(d.in[i].base, d.in[i].f64, I.off[i] + kpart(d.in[i], t, d.rC)));
       s_coef[t] = c;
+      s_coefl[perm(t)] = c;
     }
     char *op = (char *)d.out.base + I.obase * (d.out.f64 ? 16u : 8u);
     const uint32_t of = d.out.f64;
     const int sh = I.sh;
     uint32_t wmax = 0;
+    // operand v at position k of the sum, as complex128
+    auto opnd = [&](int v, uint32_t k) __attribute__((always_inline)) {
+      const uint32_t idx = s_kap[v][k] + lo[v];
+      if (v == fold) {
+        const lds_c128 c = ((const QTN_LDS lds_c128 *)(stage + soff[v]))[idx];
+        return make_double2(c.x, c.y);
+      } else if (v < NF) {
+        const float2 f = ((const float2 *)(stage + soff[v]))[idx];
+        return make_double2((double)f.x, (double)f.y);
+      }
+      return ((const double2 *)(stage + soff[v]))[idx];
+    };
+    // coefficient x operands 0 .. upto-1 at position k (the folded operand
+    // carries the coefficient)
+    auto head = [&](uint32_t k, int upto) __attribute__((always_inline)) {
+      double2 prod = fold < 0 ? s_coefl[k] : make_double2(1.0, 0.0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (v < upto) {
+          const double2 x = opnd(v, k);
+          prod = (v == 0 && fold >= 0) ? x : cmul(prod, x);
+        }
+      return prod;
+    };
+    // acc + head(k, v) x operand v at position k
+    auto mac = [&](uint32_t k, int v, double2 acc) __attribute__((always_inline)) {
+      if (v == 0 && fold >= 0) {
+        const double2 x = opnd(0, k);
+        return make_double2(acc.x + x.x, acc.y + x.y);
+      }
+      return cfma(head(k, v), opnd(v, k), acc);
+    };
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
       // operand bases of the current chunk of 16 rows: instance offset plus
       // the index part of the row bits above the lowest four
@@ -910,26 +965,16 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
         }
         __syncthreads();
         double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-        for (uint32_t k = 0; k < NKAP; ++k) {
-          double2 prod = fold < 0 ? s_coef[k] : make_double2(1.0, 0.0);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const uint32_t idx = s_kap[v][k] + lo[v];
-            double2 x;
-            if (v == fold) {
-              const lds_c128 c = ((const QTN_LDS lds_c128 *)(stage + soff[v]))[idx];
-              x = make_double2(c.x, c.y);
-            } else if (v < NF) {
-              const float2 f = ((const float2 *)(stage + soff[v]))[idx];
-              x = make_double2((double)f.x, (double)f.y);
-            } else {
-              x = ((const double2 *)(stage + soff[v]))[idx];
-            }
-            prod = (v == 0 && fold >= 0) ? x : cmul(prod, x);
+        if (NV > 1 && fact) {
+          // positions 2j and 2j+1 share the last operand's element
+#pragma unroll 2
+          for (uint32_t k = 0; k < NKAP; k += 2) {
+            const double2 inner = mac(k + 1, NV - 2, head(k, NV - 1));
+            acc = cfma(inner, opnd(NV - 1, k), acc);
           }
-          acc.x += prod.x;
-          acc.y += prod.y;
+        } else {
+#pragma unroll 4
+          for (uint32_t k = 0; k < NKAP; ++k) acc = mac(k, NV - 1, acc);
         }
         if (SCALE) {
           acc.x = ldexp(acc.x, -sh);
