@@ -758,8 +758,10 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
           for (int v = 0; v < NV; ++v) hoff[v] = dpext(ch, hmask[v]) << hshift[v];
         }
         double2 acc = make_double2(0.0, 0.0);
-        // all loads of a group of kappa values are issued before any product
-        constexpr uint32_t KU = NKAP > 4 ? 4 : NKAP;
+        // all loads of a group of kappa values are issued before any product:
+        // up to 16 loads in flight per thread (every kappa value at once
+        // when the step has few varying operands)
+        constexpr uint32_t KU = NKAP * NV <= 16 ? NKAP : (NKAP > 4 ? 4 : NKAP);
 #pragma unroll 1
         for (uint32_t kb = 0; kb < NKAP; kb += KU) {
           float2 xf[KU][NF > 0 ? NF : 1];
@@ -1631,13 +1633,17 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
             if (streaming) {
               // units of jspan x 256 elements: about 1024 blocks over the chip
               // (4 per compute unit), each walking up to 32 rows, so that the
-              // per-block set-up is paid once per 8192 outputs; measured on
-              // the n=120 step, 2048 and 512 blocks are slower
+              // per-block set-up (index tables, instance offsets and kappa
+              // coefficients, a chain of dependent loads) is paid once per up
+              // to 8192 outputs.  Measured on the n=120 steps: 2048 to 8192
+              // blocks are slower for both kernels (up to 3x for the direct
+              // ones), 256 is slower, 512 is about even.
+              const uint64_t target = 1024;
               const uint32_t rows = (1u << d.rC) >> 8;
               uint32_t jspan = 32;
-              while (jspan > 1 && (uint64_t)(rows / jspan) * Q < 1024) jspan >>= 1;
+              while (jspan > 1 && (uint64_t)(rows / jspan) * Q < target) jspan >>= 1;
               const uint64_t units = rows / jspan;
-              const uint64_t want = std::max<uint64_t>(1, 2048 / std::max<uint64_t>(Q, 1));
+              const uint64_t want = std::max<uint64_t>(1, 2 * target / std::max<uint64_t>(Q, 1));
               const dim3 grid((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
               launch_stream<SCALE>(d, grid, stream, nb, ns, s_lo, jspan);
             } else {
