@@ -939,29 +939,55 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
           if (v == fold) {
             // complex128 copy times the kappa coefficient of its run
             QTN_LDS lds_c128 *dst = (QTN_LDS lds_c128 *)(stage + soff[v]);
-            for (uint32_t e = t; e < n; e += 256) {
-              // byte offset within the operand: below 2^31 (checked by the host)
-              const uint32_t g = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
-              double2 x;
+            // two elements per trip, both loads issued before either write
+            for (uint32_t e = t; e < n; e += 512) {
+              const bool two = e + 256 < n;
+              // byte offsets within the operand: below 2^31 (checked by the host)
+              const uint32_t g0 = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
+              const uint32_t e1 = e + 256;
+              const uint32_t g1 = (((e1 >> nlo[v]) << pc[v]) + (e1 & lmask)) * esz;
+              double2 x0, x1 = make_double2(0.0, 0.0);
               if (v < NF) {
-                const float2 f = *(const float2 *)(rb + g);
-                x = make_double2((double)f.x, (double)f.y);
+                const float2 f0 = *(const float2 *)(rb + g0);
+                float2 f1 = make_float2(0.f, 0.f);
+                if (two) f1 = *(const float2 *)(rb + g1);
+                x0 = make_double2((double)f0.x, (double)f0.y);
+                x1 = make_double2((double)f1.x, (double)f1.y);
               } else {
-                x = *(const double2 *)(rb + g);
+                x0 = *(const double2 *)(rb + g0);
+                if (two) x1 = *(const double2 *)(rb + g1);
               }
-              x = cmul(x, s_coef[e >> nlo[v]]);
+              x0 = cmul(x0, s_coef[e >> nlo[v]]);
               lds_c128 c;
-              c.x = x.x;
-              c.y = x.y;
+              c.x = x0.x;
+              c.y = x0.y;
               dst[e] = c;
+              if (two) {
+                x1 = cmul(x1, s_coef[e1 >> nlo[v]]);
+                c.x = x1.x;
+                c.y = x1.y;
+                dst[e1] = c;
+              }
             }
           } else {
-            for (uint32_t e = t; e < n; e += 256) {
-              const uint32_t g = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
-              if (v < NF)
-                ((float2 *)(stage + soff[v]))[e] = *(const float2 *)(rb + g);
-              else
-                ((double2 *)(stage + soff[v]))[e] = *(const double2 *)(rb + g);
+            for (uint32_t e = t; e < n; e += 512) {
+              const bool two = e + 256 < n;
+              const uint32_t g0 = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
+              const uint32_t e1 = e + 256;
+              const uint32_t g1 = (((e1 >> nlo[v]) << pc[v]) + (e1 & lmask)) * esz;
+              if (v < NF) {
+                const float2 f0 = *(const float2 *)(rb + g0);
+                float2 f1 = make_float2(0.f, 0.f);
+                if (two) f1 = *(const float2 *)(rb + g1);
+                ((float2 *)(stage + soff[v]))[e] = f0;
+                if (two) ((float2 *)(stage + soff[v]))[e1] = f1;
+              } else {
+                const double2 x0 = *(const double2 *)(rb + g0);
+                double2 x1 = make_double2(0.0, 0.0);
+                if (two) x1 = *(const double2 *)(rb + g1);
+                ((double2 *)(stage + soff[v]))[e] = x0;
+                if (two) ((double2 *)(stage + soff[v]))[e1] = x1;
+              }
             }
           }
         }
