@@ -289,3 +289,118 @@ def test_min_fill_tie_rule_hand_derived():
     assert order == [int(t) for t in d["minfill"]]
     assert [len(s) for s in nplus] == [int(t) for t in d["minfill_nplus"]]
     assert Q.min_degree_order(adj)[0] == int(d["mindegree_first"][0])
+
+
+def test_adam_step_hand_computed():
+    """Pins MLP64.adam_step to three Adam updates of one scalar computed by hand
+    from the published rule (tests/golden/adam_scalar.txt): a dropped bias
+    correction, a misplaced eps or a wrong moment update changes the digits."""
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "adam_scalar.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    net = MLP64([np.array([[1.0]])], [np.array([0.0])])
+    for t, g, w in rows:
+        net.adam_step([np.array([[float(g)]])], [np.array([0.0])], lr=0.1, b1=0.9, b2=0.999,
+                      eps=0.1)
+        assert net.t == int(t)
+        assert abs(net.W[0][0, 0] - float(w)) <= 2e-16, (t, net.W[0][0, 0], w)
+        assert net.b[0][0] == 0.0   # a zero gradient leaves its parameter unchanged
+
+
+def _golden_costs():
+    out = []
+    for line in open(os.path.join(GOLDEN, "elimination_cost.txt")):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            order = [int(v) for v in f[3].split(",")]
+            edges = [tuple(int(v) for v in e.split("-")) for e in f[4:]]
+            out.append((f[0], int(f[1]), int(f[2]), order, edges))
+    return out
+
+
+def _adj(nv, edges):
+    adj = [set() for _ in range(nv)]
+    for a, b in edges:
+        adj[a].add(b)
+        adj[b].add(a)
+    return adj
+
+
+@pytest.mark.parametrize("name,width,work,order,edges", _golden_costs())
+def test_elimination_cost_hand_derived(name, width, work, order, edges):
+    adj = _adj(len(order), edges)
+    assert Q.elimination_cost(adj, order) == (width, work), name
+
+
+def _bucket_recount(nv, edges, order, rng):
+    """Eliminates `order` by contracting explicit random tensors bucket by
+    bucket (one 2x2 factor per edge, one 2-vector per vertex) and counts the
+    index space of every bucket product; returns (width, work, value)."""
+    factors = [((a, b), rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))) for a, b in edges]
+    factors += [((v,), rng.normal(size=2) + 1j * rng.normal(size=2)) for v in range(nv)]
+    letters = "abcdefghijklmnopqrstuvwxyz"
+    width, work = 0, 0
+    for v in order:
+        bucket = [f for f in factors if v in f[0]]
+        factors = [f for f in factors if v not in f[0]]
+        union = sorted(set().union(*[set(f[0]) for f in bucket]))
+        spec = ",".join("".join(letters[u] for u in vs) for vs, _ in bucket)
+        prod = np.einsum(spec + "->" + "".join(letters[u] for u in union), *[a for _, a in bucket])
+        assert prod.size == 1 << len(union)
+        work += prod.size
+        width = max(width, len(union) - 1)
+        out_vars = tuple(u for u in union if u != v)
+        factors.append((out_vars, prod.sum(axis=union.index(v))))
+    value = complex(np.prod([complex(a) for vs, a in factors]))
+    return width, work, value, factors
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_elimination_cost_recount_by_bucket_contraction(seed):
+    """The (width, work) that elimination_cost derives from the graph equals a
+    recount from an explicit bucket-by-bucket contraction of random tensors on
+    the same graph and order; the contraction itself equals the brute-force sum
+    over all assignments, so the recount is of a correct elimination."""
+    rng = np.random.default_rng(100 + seed)
+    nv = 8 if seed % 2 else 10
+    edges = random_regular_graph(nv, rng)
+    order = [int(v) for v in rng.permutation(nv)]
+    adj = _adj(nv, edges)
+    rec_rng = np.random.default_rng(seed)
+    width, work, value, _ = _bucket_recount(nv, edges, order, rec_rng)
+    assert Q.elimination_cost(adj, order) == (width, work)
+    # brute force with the same tensors
+    rec_rng = np.random.default_rng(seed)
+    fs = [((a, b), rec_rng.normal(size=(2, 2)) + 1j * rec_rng.normal(size=(2, 2))) for a, b in edges]
+    fs += [((v,), rec_rng.normal(size=2) + 1j * rec_rng.normal(size=2)) for v in range(nv)]
+    total = 0j
+    for bits in itertools.product((0, 1), repeat=nv):
+        term = 1 + 0j
+        for vs, arr in fs:
+            term *= arr[tuple(bits[u] for u in vs)]
+        total += term
+    assert abs(value - total) <= 1e-10 * max(1.0, abs(total))
+
+
+def test_tree_decomposition_checker_rejects_each_violation():
+    """check_tree_decomposition accepts a valid decomposition of the 4-cycle
+    and rejects one violation of each condition of Sec. II B."""
+    adj = _adj(4, [(0, 1), (1, 2), (2, 3), (3, 0)])
+    bags, parent = Q.bags_from_order(adj, [0, 1, 2, 3])
+    assert Q.check_tree_decomposition(adj, bags, parent) == 2
+    path = {0: None, 1: 0, 2: 1}           # bag tree 0 - 1 - 2
+    # (1) vertex 3 is in no bag
+    with pytest.raises(AssertionError, match=r"condition \(1\)"):
+        Q.check_tree_decomposition(adj, {0: frozenset({0, 1}), 1: frozenset({1, 2}),
+                                         2: frozenset({2, 0})}, path)
+    # (2) every vertex is covered but edge 3-0 lies in no bag
+    with pytest.raises(AssertionError, match=r"condition \(2\)"):
+        Q.check_tree_decomposition(adj, {0: frozenset({0, 1}), 1: frozenset({1, 2}),
+                                         2: frozenset({2, 3})}, path)
+    # (3) vertex 3 sits in bags 0 and 2 but not in bag 1 between them
+    with pytest.raises(AssertionError, match=r"condition \(3\)"):
+        Q.check_tree_decomposition(adj, {0: frozenset({0, 1, 3}), 1: frozenset({1, 2}),
+                                         2: frozenset({2, 3})}, path)
+    # the same bags with vertex 3 added to the middle bag are valid again
+    assert Q.check_tree_decomposition(adj, {0: frozenset({0, 1, 3}), 1: frozenset({1, 2, 3}),
+                                            2: frozenset({2, 3})}, path) == 2
