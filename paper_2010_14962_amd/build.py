@@ -1,21 +1,27 @@
-"""Compiles libqtn.so for gfx950 in-tree with hipcc."""
+"""Compiles libqtn.so for gfx950 in-tree with hipcc.
+
+Every source is compiled to an object file in its own hipcc process (in
+parallel), then the objects are linked into one shared library.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqtn.so")
+OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["planner.cpp", "api.cpp", "costmodel.cpp", "runtime.hip", "mlp.hip"]
+SOURCES = ["planner.cpp", "api.cpp", "costmodel.cpp", "ranges.cpp", "runtime.hip", "mlp.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
@@ -23,19 +29,36 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + srcs + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+def _filter(text: str) -> str:
+    return "\n".join(l for l in text.splitlines() if "packed-fp32-ops" not in l)
+
+
+def _compile(src: str) -> tuple[str, int, str]:
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
-    out = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
-                    if "packed-fp32-ops" not in l)
+    return obj, r.returncode, _filter(r.stdout + r.stderr)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    jobs = max(1, min(len(srcs), os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_compile, srcs))
+    errors = [(s, out) for s, (_, rc, out) in zip(srcs, results) if rc != 0]
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join("%s:\n%s" % e for e in errors))
+    if verbose:
+        for s, (_, _, out) in zip(srcs, results):
+            if out.strip():
+                print(out)
+    tmp = LIB + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC"] + [o for o, _, _ in results] + [
+        "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + out)
-    if verbose and out.strip():
-        print(out)
+        raise RuntimeError("link failed:\n" + _filter(r.stdout + r.stderr))
     os.replace(tmp, LIB)
     return LIB
 

@@ -519,7 +519,7 @@ int assign_storage(Schedule &s, int precision, double small_share) {
     for (auto &t : s.tensors) t.f64 = true;
     return 64;
   }
-  // bytes moved per instance by tensors of each rank, stored as complex64
+  // bytes moved per instance by tensors of each rank, stored in 8 bytes
   std::vector<double> by_rank(64, 0.0);
   double total = 0.0;
   for (const Step &st : s.steps) {

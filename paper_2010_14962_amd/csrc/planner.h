@@ -89,7 +89,7 @@ struct Tensor {
   bool leaf = false;
   bool bdep = false;       // depends on the bitstring
   bool sdep = false;       // depends on the slice
-  bool f64 = true;         // intermediates: stored as complex128 (else complex64)
+  bool f64 = true;         // intermediates: stored as complex128 (else the 64-bit shared-exponent form of the runtime)
   uint32_t selmask = 0;    // leaves: slice bits selecting the variant
   std::vector<cd> values;  // leaves: [B or 1][2^popcount(selmask)][2^rank]
   int producer = -1, last_use = -1;
@@ -201,8 +201,9 @@ inline uint64_t instances(const Tensor &t, uint64_t B, uint64_t S) {
 
 // Storage precision of every intermediate.  FP64 plans store everything as
 // complex128.  Mixed plans store the large tensors, which carry the HBM
-// traffic, as complex64 and keep the small ones (at most `small_share` of the
-// complex64 bytes) as complex128.  Returns the rank below which tensors stay
+// traffic, in 8 bytes per element (a shared 8-bit exponent and two 28-bit
+// mantissas) and keep the small ones (at most `small_share` of the 8-byte
+// bytes) as complex128.  Returns the rank below which tensors stay
 // complex128.
 int assign_storage(Schedule &s, int precision, double small_share = 0.03);
 

@@ -41,7 +41,7 @@ struct OpDesc {
   uint32_t off;           // LDS / scratch byte offset
   int16_t slot;           // LDS / scratch: exponent slot, -1 for none
   uint8_t loc;            // Loc
-  uint8_t f64;            // stored as complex128 (else complex64)
+  uint8_t f64;            // stored as complex128 (else the 64-bit shared-exponent form)
   uint32_t selmask;       // leaves: slice bits that pick the variant
 };
 static_assert(sizeof(OpDesc) == 64, "OpDesc layout");
@@ -51,7 +51,7 @@ struct PStep {
   OpDesc out;
   int nin, rC, nk;
   int nvary;              // in[0..nvary) vary with the output element
-  int nf32;               // of those, in[0..nf32) are stored as complex64
+  int nf32;               // of those, in[0..nf32) are stored in the 64-bit form
   uint32_t tiled_lds;     // > 0: run as step_tiled with this much LDS
   uint32_t wg_flags;      // in a workgroup program: 1 = every operand in LDS
   int tiled_fold;         // step_tiled: operand staged as complex128 times the
@@ -63,7 +63,7 @@ static_assert(sizeof(PStep) % 16 == 0, "PStep layout");
 //  * a gate factor: the variant of instance (b, s) is
 //    base + b * bstride + pext(s, selmask) * count, count complex128 values;
 //  * a workspace tensor made by an earlier launch: base + b * bstride +
-//    sl * sstride, complex64 or complex128; in the rescaled form its
+//    sl * sstride, 64-bit form or complex128; in the rescaled form its
 //    exponent E[b * ebstride + sl * esstride] goes to the program's slot.
 struct LeafStage {
   const void *base;
@@ -197,17 +197,46 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
   return c;
 }
 
+// 64-bit complex storage of the rescaled (mixed) form: one biased exponent
+// shared by both parts and two 28-bit two's-complement mantissas,
+//   word = E << 56 | (re & 0xFFFFFFF) << 28 | (im & 0xFFFFFFF),
+//   value = (re + i im) * 2^(E - 154);  E = 0 only in the zero word.
+// With m = max(|re|, |im|) in [2^(e-1), 2^e), E = e + 127 and the parts are
+// rounded to the nearest multiple of 2^(e-27): an absolute error of at most
+// 2^-28 |z| per part (complex64 rounds each part to 2^-24 of itself).  The
+// same eight bytes as complex64.
+__device__ __forceinline__ uint64_t enc_c64e(double2 v) {
+  const double m = fmax(fabs(v.x), fabs(v.y));
+  if (!(m > 0.0)) return 0ull;
+  int e;
+  (void)frexp(m, &e);
+  const int E = e + 127;
+  if (E < 1) return 0ull;   // below 2^-127 of the instance scale: flushed
+  const double lim = 134217727.0;  // 2^27 - 1
+  const int sh = 27 - min(e, 128);
+  const int mr = (int)fmin(fmax(rint(ldexp(v.x, sh)), -lim), lim);
+  const int mi = (int)fmin(fmax(rint(ldexp(v.y, sh)), -lim), lim);
+  return ((uint64_t)min(E, 255) << 56) | ((uint64_t)((uint32_t)mr & 0xFFFFFFFu) << 28) |
+         (uint64_t)((uint32_t)mi & 0xFFFFFFFu);
+}
+
+__device__ __forceinline__ double2 dec_c64e(uint64_t w) {
+  const int re = ((int)((uint32_t)(w >> 28) << 4)) >> 4;
+  const int im = ((int)((uint32_t)w << 4)) >> 4;
+  const int sc = (int)(uint32_t)(w >> 56) - 154;
+  return make_double2(ldexp((double)re, sc), ldexp((double)im, sc));
+}
+
 __device__ __forceinline__ double2 load_g(const void *base, uint32_t f64, uint64_t i) {
   if (f64) return ((const double2 *)base)[i];
-  const float2 f = ((const float2 *)base)[i];
-  return make_double2((double)f.x, (double)f.y);
+  return dec_c64e(((const uint64_t *)base)[i]);
 }
 
 __device__ __forceinline__ void store_g(void *base, uint32_t f64, uint64_t i, double2 v) {
   if (f64)
     ((double2 *)base)[i] = v;
   else
-    ((float2 *)base)[i] = make_float2((float)v.x, (float)v.y);
+    ((uint64_t *)base)[i] = enc_c64e(v);
 }
 
 // Exponent e with 2^(e-1) <= x < 2^e for the positive float with bits `b`
@@ -217,10 +246,12 @@ __device__ __forceinline__ int exp_of_bits(uint32_t b) {
   return be == 0 ? 0 : be - 126;
 }
 
-// Exponent field of the larger component magnitude of the value as stored.
+// Float exponent field of the larger component magnitude, rounded to float
+// (an upper bound on the stored value's binade in either storage form).
 __device__ __forceinline__ uint32_t max_bits(double2 v, uint32_t f64) {
-  const float ax = f64 ? (float)fabs(v.x) : fabsf((float)v.x);
-  const float ay = f64 ? (float)fabs(v.y) : fabsf((float)v.y);
+  (void)f64;
+  const float ax = (float)fabs(v.x);
+  const float ay = (float)fabs(v.y);
   return max(__float_as_uint(ax), __float_as_uint(ay)) & 0x7F800000u;
 }
 
@@ -513,8 +544,7 @@ __device__ __forceinline__ double2 stage_load(const QTN_LDS LeafStage &L, uint32
   if (L.global) {
     const uint64_t o = (uint64_t)b * L.bstride + (uint64_t)sl * L.sstride + i;
     if (L.f64) return ((const double2 *)L.base)[o];
-    const float2 f = ((const float2 *)L.base)[o];
-    return make_double2((double)f.x, (double)f.y);
+    return dec_c64e(((const uint64_t *)L.base)[o]);
   }
   return ((const double2 *)L.base)[b * L.bstride + (uint64_t)dpext(s, L.selmask) * L.count + i];
 }
@@ -734,7 +764,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
       s_coef[t] = c;
     }
     __syncthreads();
-    // per-lane operand pointers for this instance; in[0..NF) are complex64
+    // per-lane operand pointers for this instance; in[0..NF) are in the 64-bit form
     const char *vp[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
@@ -764,7 +794,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
         constexpr uint32_t KU = NKAP * NV <= 16 ? NKAP : (NKAP > 4 ? 4 : NKAP);
 #pragma unroll 1
         for (uint32_t kb = 0; kb < NKAP; kb += KU) {
-          float2 xf[KU][NF > 0 ? NF : 1];
+          uint64_t xf[KU][NF > 0 ? NF : 1];
           double2 xd[KU][NV - NF > 0 ? NV - NF : 1];
 #pragma unroll
           for (uint32_t kk = 0; kk < KU; ++kk) {
@@ -772,7 +802,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
             for (int v = 0; v < NV; ++v) {
               const uint32_t idx = hoff[v] + s_mid[v][j] + s_kap[v][kb + kk];
               if (v < NF)
-                xf[kk][v < NF ? v : 0] = ((const float2 *)vp[v])[idx];
+                xf[kk][v < NF ? v : 0] = ((const uint64_t *)vp[v])[idx];
               else
                 xd[kk][v >= NF ? v - NF : 0] = ((const double2 *)vp[v])[idx];
             }
@@ -784,9 +814,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
             double2 prod = s_coef[kb + kk];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-              const double2 x = v < NF ? make_double2((double)xf[kk][v < NF ? v : 0].x,
-                                                      (double)xf[kk][v < NF ? v : 0].y)
-                                       : xd[kk][v >= NF ? v - NF : 0];
+              const double2 x = v < NF ? dec_c64e(xf[kk][v < NF ? v : 0]) : xd[kk][v >= NF ? v - NF : 0];
               prod = cmul(prod, x);
             }
             acc.x += prod.x;
@@ -860,7 +888,7 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
     hmask[v] = cm >> 12;
     hshift[v] = __popc(cm & 4095u);
     soff[v] = bytes;
-    bytes += (1u << (nkv[v] + nlo[v])) * (v < NF && !(FOLD && v == 0) ? 8u : 16u);
+    bytes += (1u << (nkv[v] + nlo[v])) * 16u;   // staged as complex128
   }
   constexpr int fold = FOLD ? 0 : -1;
   const uint64_t Q = (uint64_t)nb * ns;
@@ -885,14 +913,8 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
     // operand v at position k of the sum, as complex128
     auto opnd = [&](int v, uint32_t k) __attribute__((always_inline)) {
       const uint32_t idx = s_kap[v][k] + lo[v];
-      if (v == fold) {
-        const lds_c128 c = ((const QTN_LDS lds_c128 *)(stage + soff[v]))[idx];
-        return make_double2(c.x, c.y);
-      } else if (v < NF) {
-        const float2 f = ((const float2 *)(stage + soff[v]))[idx];
-        return make_double2((double)f.x, (double)f.y);
-      }
-      return ((const double2 *)(stage + soff[v]))[idx];
+      const lds_c128 c = ((const QTN_LDS lds_c128 *)(stage + soff[v]))[idx];
+      return make_double2(c.x, c.y);
     };
     // coefficient x operands 0 .. upto-1 at position k (the folded operand
     // carries the coefficient)
@@ -936,58 +958,38 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
           const char *rb = cbase[v] + (uint64_t)__builtin_amdgcn_readfirstlane(s_mid[v][row & 15u]) * esz;
           const uint32_t n = 1u << (nkv[v] + nlo[v]);
           const uint32_t lmask = (1u << nlo[v]) - 1u;
-          if (v == fold) {
-            // complex128 copy times the kappa coefficient of its run
-            QTN_LDS lds_c128 *dst = (QTN_LDS lds_c128 *)(stage + soff[v]);
-            // two elements per trip, both loads issued before either write
-            for (uint32_t e = t; e < n; e += 512) {
-              const bool two = e + 256 < n;
-              // byte offsets within the operand: below 2^31 (checked by the host)
-              const uint32_t g0 = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
-              const uint32_t e1 = e + 256;
-              const uint32_t g1 = (((e1 >> nlo[v]) << pc[v]) + (e1 & lmask)) * esz;
-              double2 x0, x1 = make_double2(0.0, 0.0);
-              if (v < NF) {
-                const float2 f0 = *(const float2 *)(rb + g0);
-                float2 f1 = make_float2(0.f, 0.f);
-                if (two) f1 = *(const float2 *)(rb + g1);
-                x0 = make_double2((double)f0.x, (double)f0.y);
-                x1 = make_double2((double)f1.x, (double)f1.y);
-              } else {
-                x0 = *(const double2 *)(rb + g0);
-                if (two) x1 = *(const double2 *)(rb + g1);
-              }
-              x0 = cmul(x0, s_coef[e >> nlo[v]]);
-              lds_c128 c;
-              c.x = x0.x;
-              c.y = x0.y;
-              dst[e] = c;
-              if (two) {
-                x1 = cmul(x1, s_coef[e1 >> nlo[v]]);
-                c.x = x1.x;
-                c.y = x1.y;
-                dst[e1] = c;
-              }
+          // every operand is staged as complex128 (the 64-bit stored form is
+          // decoded here, once per element and row, not in the kappa loop);
+          // the folded operand is multiplied by the kappa coefficient of its
+          // run.  Two elements per trip, both loads issued before either write.
+          QTN_LDS lds_c128 *dst = (QTN_LDS lds_c128 *)(stage + soff[v]);
+          for (uint32_t e = t; e < n; e += 512) {
+            const bool two = e + 256 < n;
+            // byte offsets within the operand: below 2^31 (checked by the host)
+            const uint32_t g0 = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
+            const uint32_t e1 = e + 256;
+            const uint32_t g1 = (((e1 >> nlo[v]) << pc[v]) + (e1 & lmask)) * esz;
+            double2 x0, x1 = make_double2(0.0, 0.0);
+            if (v < NF) {
+              const uint64_t w0 = *(const uint64_t *)(rb + g0);
+              uint64_t w1 = 0ull;
+              if (two) w1 = *(const uint64_t *)(rb + g1);
+              x0 = dec_c64e(w0);
+              x1 = dec_c64e(w1);
+            } else {
+              x0 = *(const double2 *)(rb + g0);
+              if (two) x1 = *(const double2 *)(rb + g1);
             }
-          } else {
-            for (uint32_t e = t; e < n; e += 512) {
-              const bool two = e + 256 < n;
-              const uint32_t g0 = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
-              const uint32_t e1 = e + 256;
-              const uint32_t g1 = (((e1 >> nlo[v]) << pc[v]) + (e1 & lmask)) * esz;
-              if (v < NF) {
-                const float2 f0 = *(const float2 *)(rb + g0);
-                float2 f1 = make_float2(0.f, 0.f);
-                if (two) f1 = *(const float2 *)(rb + g1);
-                ((float2 *)(stage + soff[v]))[e] = f0;
-                if (two) ((float2 *)(stage + soff[v]))[e1] = f1;
-              } else {
-                const double2 x0 = *(const double2 *)(rb + g0);
-                double2 x1 = make_double2(0.0, 0.0);
-                if (two) x1 = *(const double2 *)(rb + g1);
-                ((double2 *)(stage + soff[v]))[e] = x0;
-                if (two) ((double2 *)(stage + soff[v]))[e1] = x1;
-              }
+            if (v == fold) x0 = cmul(x0, s_coef[e >> nlo[v]]);
+            lds_c128 c;
+            c.x = x0.x;
+            c.y = x0.y;
+            dst[e] = c;
+            if (two) {
+              if (v == fold) x1 = cmul(x1, s_coef[e1 >> nlo[v]]);
+              c.x = x1.x;
+              c.y = x1.y;
+              dst[e1] = c;
             }
           }
         }
@@ -1391,7 +1393,7 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     d.nk = S_.nk;
     // operands whose index depends on the output element come first
     const uint32_t cbits = (S_.rC >= 32) ? 0xffffffffu : ((1u << S_.rC) - 1u);
-    // order: varying complex64, varying complex128, then the rest
+    // order: varying 64-bit, varying complex128, then the rest
     std::vector<size_t> ord;
     auto vary = [&](size_t i) { return (S_.mask[i] & cbits) != 0; };
     auto is32 = [&](size_t i) { return !sch.tensors[S_.in[i]].leaf && !sch.tensors[S_.in[i]].f64; };
@@ -1506,7 +1508,7 @@ static uint32_t tiled_lds_bytes(const PStep &d) {
     // byte offsets within one operand instance are computed in 32 bits
     if ((uint64_t)(v < d.nf32 ? 8u : 16u) << __builtin_popcount(in.mask) >= (1ull << 31)) return 0;
     staged += n;
-    bytes += n * (v < d.nf32 && v != d.tiled_fold ? 8u : 16u);
+    bytes += n * 16u;   // staged as complex128
   }
   const uint64_t direct = (uint64_t)d.nvary * 256u << d.nk;
   if (3 * staged > direct || bytes > 48 * 1024) return 0;
@@ -1516,7 +1518,7 @@ static uint32_t tiled_lds_bytes(const PStep &d) {
 template <bool SCALE, int NK, int NV>
 static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint32_t nb, uint32_t ns,
                              uint64_t s_lo, uint32_t jspan) {
-  // NF = number of complex64 operands among the NV varying ones
+  // NF = number of 64-bit-form operands among the NV varying ones
   switch (d.nf32) {
 #define QTN_NF(F)                                                                                  \
   case F:                                                                                          \
