@@ -7,10 +7,14 @@ is one contraction over all 2^k slices of all 8 bitstrings (the whole hot
 path: slice set-up, every contraction step, the FP64 slice sum, the partials
 in host memory), one synchronous qtn_contract (graph replay) per step.  The
 same steps enqueued back to back with qtn_contract_async are timed as
-well.  The mixed form (complex64 storage
-of the large tensors with per-instance power-of-two rescaling, FP64
-arithmetic) is the headline; the plain FP64 GPU contraction is timed beside
-it.
+well.  The mixed form (64-bit shared-exponent storage of the large tensors
+with per-instance power-of-two rescaling, FP64 arithmetic) is the headline;
+the plain FP64 GPU contraction is timed beside it.
+
+Two sliced workloads follow in the same line ("sliced"): n = 80, p = 2 with
+k = 16 (65,536 slices) and the same 120-qubit instance with k = 16 (8 x
+65,536 slice contractions), each in both forms, with the error of the
+[0, 1024) subset sums against the oracle and the oracle's slice rate.
 
 Prints one JSON line.  Single GPU only.
 """
@@ -120,6 +124,115 @@ def cpu_baseline(inst, cut, order, budget_s=20.0):
             "cpu_seconds": sum(r[1] for r in res), "wall_seconds": wall}, vals
 
 
+def _subset_worker(args):
+    """Oracle slice values of one bitstring over a range, on one host core."""
+    n, edges, p, gamma, beta, x, cut, order, slices = args
+    from oracle import qaoa as Q
+    t = time.perf_counter()
+    vals = [Q.slice_partial(n, edges, p, gamma, beta, x, cut, s, order=order) for s in slices]
+    return vals, time.perf_counter() - t
+
+
+def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
+    """One sliced workload: every slice of every bitstring per contraction,
+    mixed and FP64 with the same cut, the error of the [0, 1024) subset sums
+    against the oracle, and the oracle's slice rate on that subset."""
+    import torch
+    from instances import search_params, workload_instance
+    from paper_2010_14962_amd import plan_instance
+    inst = workload_instance(name, seed=seed)
+    m = inst.meta
+    t0 = time.perf_counter()
+    mixed = plan_instance(inst, k=m["k"], max_rank=m["max_rank"], precision="fp32", **search_params(name))
+    plan_s = time.perf_counter() - t0
+    cut = mixed.cut()
+    info = mixed.info()
+    k, B = info["k"], inst.n_bitstrings
+    nsl = 1 << k
+    f64 = plan_instance(inst, cut_vars=cut, precision="fp64")
+    S = min(nsl, slices_per_wave)
+    stream = torch.cuda.current_stream().cuda_stream
+    info_f = {"flops": 2.0 ** info["log2_flops"]}
+    out = {"workload": name, "n": inst.n, "p": inst.p, "bitstrings": B, "k": k,
+           "slices_per_amplitude": nsl, "slice_contractions_per_step": B * nsl,
+           "max_slice_rank": info["width"], "slices_per_wave": S, "plan_s": plan_s,
+           "log2_flops_per_slice": info["log2_flops"], "alg_bytes_per_slice": info["bytes_per_slice"]}
+    sub = min(1024, nsl)
+    res = {}
+    for tag, plan in (("mixed", mixed), ("fp64", f64)):
+        plan.bind_torch(S)
+        plan.set_graphs(True)
+        plan.contract(0, nsl, stream)           # capture and warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            vals = plan.contract(0, nsl, stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        res[tag] = [p.value() for p in plan.contract(0, sub, stream)]
+        out[tag] = {"slices_per_sec": B * nsl * reps / el, "amplitudes_per_sec": B * reps / el,
+                    "ms_per_step": 1e3 * el / reps}
+        print("# %s %s: %.1f ms per contraction of %d slice instances" %
+              (name, tag, 1e3 * el / reps, B * nsl), file=sys.stderr, flush=True)
+        if tag == "mixed":
+            # whole-contraction roofline from the plan's algorithmic work per
+            # slice (flops and bytes of every step, all bitstrings) and the
+            # graph-replay time
+            flops = info_f["flops"] * nsl
+            byts = info["bytes_per_slice"] * nsl
+            tfs = flops / (el / reps) / 1e12
+            gbs = byts / (el / reps) / 1e9
+            f_alu, f_hbm = tfs / FP64_VECTOR_PEAK_TFLOPS, gbs / HBM_PEAK_GBS
+            out["roofline"] = {
+                "kernel": "whole contraction (all launches of all waves)",
+                "bound": "alu" if f_alu > f_hbm else "hbm",
+                "achieved": tfs if f_alu > f_hbm else gbs,
+                "peak": FP64_VECTOR_PEAK_TFLOPS if f_alu > f_hbm else HBM_PEAK_GBS,
+                "unit": "TFLOP/s" if f_alu > f_hbm else "GB/s",
+                "frac": max(f_alu, f_hbm), "fp64_TFLOPs": tfs, "hbm_GBs": gbs,
+                "alg_flops_per_step": flops, "alg_bytes_per_step": byts}
+        plan.close()
+    out["mixed_over_fp64"] = out["mixed"]["slices_per_sec"] / out["fp64"]["slices_per_sec"]
+    if with_cpu:
+        cores = max(1, min(16, os.cpu_count() or 1))
+        order = plan_instance(inst, cut_vars=cut).order()
+        nsub = max(sub, min(nsl, 4 * cores))
+        work, owner = [], []
+        chunk = max(1, nsub // (4 * cores))
+        for b in range(B):
+            for lo in range(0, nsub, chunk):
+                work.append((inst.n, inst.edges, inst.p, inst.gamma, inst.beta, inst.bitstrings[b], cut,
+                             order, list(range(lo, min(nsub, lo + chunk)))))
+                owner.append(b)
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            got = pool.map(_subset_worker, work)
+        wall = time.perf_counter() - t0
+        from oracle.qaoa import neumaier_sum
+        per_b = [[] for _ in range(B)]
+        for (vals, _), b in zip(got, owner):
+            per_b[b].extend(vals)
+        errs = {"mixed": [], "fp64": []}
+        kappa = []
+        for b in range(B):
+            sl = per_b[b][:sub]
+            re, rc = neumaier_sum(v.real for v in sl)
+            im, ic = neumaier_sum(v.imag for v in sl)
+            ref = complex(re + rc, im + ic)
+            kappa.append(sum(abs(v) for v in sl) / abs(ref))
+            for tag in errs:
+                errs[tag].append(abs(res[tag][b] - ref) / abs(ref))
+        out["subset"] = {"slices": sub, "max_rel_err_mixed_vs_oracle": max(errs["mixed"]),
+                         "max_rel_err_fp64_vs_oracle": max(errs["fp64"]), "max_kappa": max(kappa)}
+        out["cpu_baseline"] = {"value": B * nsub / wall, "unit": "slices/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "slices [0, %d) of all %d bitstrings, complex128 variable "
+                                         "elimination with the plan's cut and order, %d worker "
+                                         "processes" % (nsub, B, cores),
+                               "cpu_seconds": sum(g[1] for g in got), "wall_seconds": wall}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +243,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--slices-per-wave", type=int, default=4096)
+    ap.add_argument("--no-sliced", action="store_true",
+                    help="skip the sliced workloads (n=80 p=2 k=16, n=120 p=1 k=16)")
+    ap.add_argument("--sliced-reps", type=int, default=3)
+    ap.add_argument("--sliced-child", default=None,
+                    help="internal: run one sliced workload and print its JSON object")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -144,6 +262,10 @@ def main():
     from paper_2010_14962_amd import plan_instance, qtn_plan
 
     torch.cuda.set_device(0)
+    if args.sliced_child:
+        print(json.dumps(sliced_row(args.sliced_child, args.seed, args.slices_per_wave,
+                                    args.sliced_reps, not args.no_cpu_baseline)), flush=True)
+        return
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib << 20
         src = torch.ones(n, dtype=torch.uint8, device="cuda")
@@ -266,12 +388,14 @@ def main():
     line = {
         "metric": METRIC, "value": amps_per_s, "unit": "amplitudes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": inst.n, "p": inst.p, "bitstrings": B,
                    "k": k, "slices_per_amplitude": nsl, "max_slice_rank": info["width"],
                    "seed": args.seed, "slices_per_wave": S, "graph": "random 3-regular",
-                   "precision": "fp32 + per-slice power-of-two rescale, fp64 slice sum"},
+                   "precision": "mixed: large tensors stored in 8 bytes (shared 8-bit exponent, "
+                                "two 28-bit mantissas) with per-instance power-of-two rescaling, "
+                                "fp64 arithmetic, fp64 compensated slice sum"},
         "slices_per_sec": slices_per_s,
         "timing": "one synchronous qtn_contract per step (graph replay, partials in host memory)",
         "pipelined_ms_per_step": 1e3 * el_pipe / args.steps,
@@ -295,6 +419,26 @@ def main():
             line["max_rel_err_mixed_vs_oracle"] = max(errs)
             line["max_rel_err_fp64_vs_oracle"] = max(abs(amps64[j % B] - v) / abs(v)
                                                      for j, v in enumerate(vals[:B]))
+    if not args.no_sliced:
+        # each sliced workload in a child process: whatever happens there, the
+        # headline line above is printed
+        import subprocess
+        line["sliced"] = []
+        for nm in ("qaoa_n80_p2_k16", "qaoa_n120_p1_b8_k16"):
+            cmd = [sys.executable, os.path.abspath(__file__), "--sliced-child", nm, "--seed", str(args.seed),
+                   "--slices-per-wave", str(args.slices_per_wave), "--sliced-reps", str(args.sliced_reps)]
+            if args.no_cpu_baseline:
+                cmd.append("--no-cpu-baseline")
+            try:
+                r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+                sys.stderr.write(r.stderr)
+                rows = [l for l in r.stdout.splitlines() if l.startswith("{")]
+                if r.returncode == 0 and rows:
+                    line["sliced"].append(json.loads(rows[-1]))
+                else:
+                    line["sliced"].append({"workload": nm, "error": "exit status %d" % r.returncode})
+            except subprocess.TimeoutExpired:
+                line["sliced"].append({"workload": nm, "error": "time limit"})
     print(json.dumps(line), flush=True)
 
 

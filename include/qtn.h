@@ -51,18 +51,19 @@ enum {
 /*
  * Precision forms.  QTN_FP64: every tensor complex128, FP64 arithmetic, no
  * rescaling.  QTN_FP32 (mixed): the large slice tensors, which carry the HBM
- * traffic, are stored as complex64 with a per-instance power-of-two exponent
- * (rescaled after every grid-wide step); small tensors (under 3% of the
- * bytes), LDS-resident program tensors and the gate factors stay complex128;
- * all products and sums run in FP64 registers.  The slice sum is always FP64.
- * QTN_3XBF16 (split-BF16 matrix-core products) is reserved: the schedules
- * built here sum at most 4 variables per step (Eq. (1) with |kappa| <= 4),
- * an arithmetic intensity far below the matrix-core ridge, so no step is
- * dense enough for it; qtn_plan rejects it with QTN_EINVAL.
+ * traffic, are stored in eight bytes per element, as many as complex64: one
+ * 8-bit exponent shared by the real and imaginary parts and two 28-bit
+ * two's-complement mantissas (absolute error at most 2^-28 |z| per part,
+ * against 2^-24 of each part for complex64), with a per-instance power-of-two
+ * exponent (rescaled after every grid-wide step); small tensors (under 3% of
+ * the bytes), LDS-resident program tensors and the gate factors stay
+ * complex128; all products and sums run in FP64 registers.  The slice sum is
+ * always FP64.
  */
 enum { QTN_FP64 = 0, QTN_FP32 = 1, QTN_3XBF16 = 2 };
 
 typedef struct qtn_plan_s qtn_plan_t; /* opaque, owned by the library */
+typedef struct qtn_mlp_s qtn_mlp_t;   /* learned cut-set cost model (below) */
 
 /* Compensated FP64 sum of slice results: value = (re + re_comp, im + im_comp). */
 typedef struct {
@@ -87,12 +88,23 @@ typedef struct {
   int32_t precision;         /* QTN_FP64, QTN_FP32 or QTN_3XBF16                           */
   int32_t fuse_chains;       /* 1: sum chains of trivial buckets in one step (default 1)   */
   int32_t exec_mode;         /* -1 auto (= 0), 0 grid-wide steps, 1 one workgroup per instance */
+  int32_t use_cost_model;    /* 1: the cut search ranks its offspring with cost_model and     */
+                             /*    scores only the best N-1 exactly (see qtn_cut_search)       */
+  int32_t offspring_factor;  /* offspring per kept individual with use_cost_model (16)      */
+  qtn_mlp_t *cost_model;     /* trained model (qtn_mlp_create, QTN_COST_FEATURES inputs)     */
+  int32_t density_matrix;    /* 1: the density-matrix network of Sec. II A (Markov-Shi
+                                tensors over 4-valued edges, each edge the pair of a ket
+                                variable v and its bra copy v + n p); the result is
+                                |amplitude|^2 (real part of the partials); k and
+                                cut_vars count 4-valued edges (ket ids), each cut gives
+                                4 slices, so 4^k in all; qtn_plan_cut lists the 2 k
+                                binary variables, ket ids first                          */
 } qtn_plan_opts;
 
 typedef struct {
   uint32_t n, p, n_vars, n_bitstrings;
   int32_t k;                 /* number of cut variables */
-  int32_t width;             /* largest rank of a slice tensor (min-fill width of G - C)  */
+  int32_t width;             /* largest rank of a slice tensor the schedule materialises  */
   int32_t n_steps;           /* contraction steps per slice                               */
   int32_t n_tensors;
   double log2_flops;         /* real flops per slice-contraction (all bitstrings)          */
@@ -107,16 +119,21 @@ typedef struct {
   int32_t n_launches_wide;   /* kernel launches per wave, grid-wide mode                  */
   uint32_t slice_lds_bytes;  /* LDS per workgroup, one-workgroup-per-instance mode        */
   double slice_scratch_bytes;/* global scratch per workgroup, same mode                   */
+  int32_t mf_width;          /* width of the min-fill order on G - C, Sec. II B (largest bag
+                                minus one; the cut search's fitness); width <= mf_width + 1 */
 } qtn_plan_info;
 
 /* Fills defaults: k = -1, max_rank = 0, k_max = 24, cut_vars = NULL, seed = 0,
  * ga_pop = 11, ga_iters = 4 (Sec. IV A), precision = QTN_FP64, fuse_chains = 1,
- * exec_mode = -1. */
+ * exec_mode = -1, use_cost_model = 0, offspring_factor = 16, cost_model = NULL,
+ * density_matrix = 0. */
 void qtn_plan_opts_default(qtn_plan_opts *opts);
 
 /*
- * Build a host-side plan (no device calls).  Sec. II A (network), Sec. II B
- * (elimination order), Sec. III A (cut and slice), Sec. III B (cut search).
+ * Build a host-side plan.  Sec. II A (network), Sec. II B (elimination order),
+ * Sec. III A (cut and slice), Sec. III B (cut search, Algorithm 1).  No device
+ * call is made, except that with use_cost_model the model ranks candidates on
+ * the current device (the model's own buffers; nothing else is allocated).
  *   graph        simple undirected graph (no self-loops or repeated edges)
  *   p            QAOA depth, >= 1
  *   gamma, beta  p angles each, finite
@@ -130,18 +147,29 @@ int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
              uint32_t n_bitstrings, const qtn_plan_opts *opts,
              qtn_plan_t **out);
 
+/* Frees the plan and the constant device buffers it uploaded (leaf factors,
+ * program descriptors, pinned partials); the bound workspace stays the
+ * caller's.  NULL is ignored. */
 void qtn_plan_destroy(qtn_plan_t *plan);
 
+/* Plan summary: cut size k, width (Sec. II B: largest bag minus one = largest
+ * slice tensor rank), algorithmic flops and bytes per slice of the schedule
+ * (Eq. (1) steps), and the execution structure.  Host only. */
 int qtn_plan_query(const qtn_plan_t *plan, qtn_plan_info *info);
 
-/* Copies the k cut variable ids (ascending) into cut[0..k). */
+/* Copies the k cut variable ids (ascending) into cut[0..k): the index
+ * variables fixed per slice (Sec. III A, Fig. 3).  QTN_EINVAL if capacity < k. */
 int qtn_plan_cut(const qtn_plan_t *plan, uint32_t *cut, uint32_t capacity);
 
-/* Copies the elimination order of the free variables (n_vars - k ids). */
+/* Copies the elimination order of the free variables (n_vars - k ids), the
+ * min-fill order on G - C that fixes the contraction order (Sec. II B). */
 int qtn_plan_order(const qtn_plan_t *plan, uint32_t *order, uint32_t capacity);
 
 /*
- * Exports the contraction schedule for inspection.  For step t:
+ * Exports the contraction schedule for inspection: the chain of contractions
+ * of Eq. (1), C[out] = sum over kappa of the product of the inputs, one per
+ * bucket of the elimination order (Sec. II B), shared by every slice
+ * (Sec. III A: the sub-networks have identical structure).  For step t:
  *   rec[0] = output tensor id, rec[1] = number of inputs, rec[2] = |kappa|,
  *   rec[3] = output rank, rec[4] = class (0 E, 1 G), rec[5..5+8) = input ids
  *   (-1 unused), rec[13..13+8) = input bit masks over the step index
@@ -158,12 +186,13 @@ int qtn_plan_order(const qtn_plan_t *plan, uint32_t *order, uint32_t capacity);
 int qtn_plan_export(const qtn_plan_t *plan, int32_t *steps, uint32_t step_cap,
                     int32_t *tensors, uint32_t tensor_cap);
 
-/* Summed variables of step `step` (most significant first) into kappa[0..nk). */
+/* Summed variables of step `step` (most significant first) into kappa[0..nk):
+ * the index j of Eq. (1) (several at once in a fused step). */
 int qtn_plan_kappa(const qtn_plan_t *plan, int32_t step, int32_t *kappa, uint32_t capacity);
 
 /*
- * Integer index tables of input `input` of step `step`, as uploaded to the
- * device: table[0..256) = pext(c & 255, cmask & 255), table[256..272) =
+ * Integer index tables of input `input` of step `step` (the index maps of the
+ * Eq. (1) contraction, in the form the device derives them in):  table[0..256) = pext(c & 255, cmask & 255), table[256..272) =
  * pext(u << 8, cmask) for u < 16, table[272] = cmask >> 12, table[273] =
  * popcount(cmask & 4095), table[274..274+2^nk) = pext(kappa, kmask) <<
  * popcount(cmask), where cmask / kmask are the input's mask bits over the
@@ -174,14 +203,19 @@ int qtn_plan_index_table(const qtn_plan_t *plan, int32_t step, int32_t input,
                          uint32_t *table, uint32_t capacity, uint32_t *count);
 
 /* Leaf values (FP64) of tensor `tensor`: [bitstring or 1][variant][2^rank]
- * complex, interleaved re/im; `count` receives the number of complex values. */
+ * complex, interleaved re/im; `count` receives the number of complex values.
+ * The gate tensors of Sec. II A (Fig. 1), merged per bucket; a variant is one
+ * assignment of the cut variables it holds (the restricted tensors of Fig. 3). */
 int qtn_plan_leaf_values(const qtn_plan_t *plan, int32_t tensor, double *values,
                          uint64_t capacity, uint64_t *count);
 
 /*
  * Device workspace needed to contract `slices_per_wave` slices of every
  * bitstring at once (intermediates with liveness reuse, scale exponents,
- * per-slice results).  Pure host computation.
+ * per-slice results).  Pure host computation.  The slices of one wave are
+ * the identical-structure sub-networks of Sec. III A processed together, the
+ * paper's rounds of subgraphs per core count; slices_per_wave is clamped to
+ * [1, 2^k].  QTN_EINVAL for 0 or above 2^24.
  */
 int qtn_plan_workspace_bytes(const qtn_plan_t *plan, uint64_t slices_per_wave,
                              uint64_t *bytes);
@@ -189,8 +223,10 @@ int qtn_plan_workspace_bytes(const qtn_plan_t *plan, uint64_t slices_per_wave,
 /*
  * Binds caller-owned device memory (e.g. a torch tensor) of `bytes` bytes,
  * 256-byte aligned, to the plan, with `slices_per_wave` slices per wave, and
- * uploads the plan's constants to the current device.  The memory must stay
- * valid until the plan is destroyed or rebound.
+ * uploads the plan's constants (gate tensors of Sec. II A, step descriptors
+ * of the Eq. (1) schedule) to the current device.  The memory must stay valid
+ * until the plan is destroyed or rebound.  QTN_ENOMEM if `bytes` is below
+ * qtn_plan_workspace_bytes, QTN_EINVAL for misalignment.
  */
 int qtn_plan_bind_workspace(qtn_plan_t *plan, void *device_ptr, uint64_t bytes,
                             uint64_t slices_per_wave);
@@ -233,6 +269,30 @@ int qtn_contract_async(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi, v
  */
 int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
 
+/*
+ * Autotuner of the launch configuration: for every grid-wide streaming step
+ * of the bound plan it times (HIP events on `stream`, 5 launches each) the
+ * block count over the chip (256, 512, 1024, 2048) and, where the LDS-staged
+ * kernel applies, that kernel against the direct one, and keeps the fastest
+ * for later contractions.  cache_path (or NULL): a text file of known choices,
+ * one line per step signature ("<hex signature> <blocks> <direct> <us>"); steps
+ * found there are not measured, new choices are appended.  Runs one
+ * contraction of the first wave first (its results are discarded) and leaves
+ * the workspace ready for the next call; drops the captured graph.  Not while
+ * timing is on (QTN_ESTATE).  The choices change the block partition only,
+ * not the arithmetic of any output element; a step that folds the closing
+ * chain groups its partial sums by block, so the amplitude may change in its
+ * last bits.
+ */
+typedef struct {
+  uint32_t steps;      /* streaming steps of the plan                      */
+  uint32_t measured;   /* configurations timed                             */
+  uint32_t cached;     /* steps whose choice came from the cache           */
+  double default_us;   /* summed time of the measured steps, default config */
+  double tuned_us;     /* the same steps with the chosen configuration     */
+} qtn_tune_stats;
+int qtn_plan_autotune(qtn_plan_t *plan, void *stream, const char *cache_path, qtn_tune_stats *stats);
+
 /* Accumulated timing of the streaming step kernels (grid-wide steps whose
  * output holds at least 2^8 elements per instance: step_stream and
  * step_tiled), measured with HIP events recorded on the launch's stream
@@ -257,7 +317,11 @@ int qtn_plan_set_timing(qtn_plan_t *plan, int enable);
 int qtn_plan_timing(const qtn_plan_t *plan, qtn_kernel_timing *out);
 
 /* The same counters restricted to schedule step `step` (zero if the step
- * was not timed). */
+ * was not timed).  step = -1 gives the launches of workgroup programs
+ * (trees of small steps, one workgroup per instance), timed the same way and
+ * not part of the totals above; their algorithmic bytes are the gate factors,
+ * workspace and scratch tensors each item reads or writes outside LDS, once
+ * each, and their flops those of every step in the program. */
 int qtn_plan_step_timing(const qtn_plan_t *plan, int32_t step, qtn_kernel_timing *out);
 
 /* Name of the kernel instance that runs grid-wide step `step` under the
@@ -287,8 +351,6 @@ int qtn_cost_features(const qtn_graph *graph, uint32_t p, const uint32_t *cut_se
 int qtn_cost_exact(const qtn_graph *graph, uint32_t p, const uint32_t *cut_sets,
                    uint32_t n_sets, uint32_t k, int32_t *width, double *log2_cost,
                    int32_t threads);
-
-typedef struct qtn_mlp_s qtn_mlp_t;
 
 /* Multilayer perceptron in_dim -> hidden (x n_hidden, ReLU) -> out_dim on the
  * current device, FP32, He-initialised from `seed`.  Dense layers run on FP32
@@ -337,7 +399,72 @@ int qtn_cut_search(const qtn_graph *graph, uint32_t p, uint32_t k, int32_t pop, 
                    uint64_t seed, qtn_mlp_t *model, int32_t offspring_factor,
                    uint32_t *cut_out, qtn_search_stats *stats);
 
-/* Error-free combination of two partials (TwoSum on each component). */
+/*
+ * Several circuits (plans of different graphs, depths, cut sets and bitstring
+ * counts) in one persistent launch: the whole-schedule workgroup programs of
+ * all plans run in one kernel whose workgroups take (plan, bitstring, slice)
+ * items from all of them, as the paper's cores take subgraphs (Sec. III A),
+ * then each plan's slice sum follows; the call waits for `stream`.  Every
+ * plan must be bound (qtn_plan_bind_workspace) in one-workgroup-per-instance
+ * mode (exec_mode = 1), on the current device, with slice_hi[i] - slice_lo[i]
+ * at most its slices per wave, and all plans in the same precision form;
+ * a plan may appear once.  out receives the partials of plan 0's bitstrings,
+ * then plan 1's, and so on (n_bitstrings of each); an empty range gives
+ * zeros.  At most 32 plans.  The result of each plan equals its own
+ * qtn_contract over the same range bit for bit.
+ */
+int qtn_batch_contract(qtn_plan_t *const *plans, uint32_t n_plans, const uint64_t *slice_lo,
+                       const uint64_t *slice_hi, void *stream, qtn_partial *out);
+
+/* ---------------------------------------------------------------------------
+ * Range-partitioned contraction with recovery.  The slices are independent
+ * and the master sums one value per slice (Sec. III A); missing slices are
+ * recovered by contracting them again (Sec. V).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  uint64_t ranges;      /* ranges of [0, 2^k)                                   */
+  uint64_t contracted;  /* ranges contracted by this call                       */
+  uint64_t resumed;     /* ranges read from the checkpoint                      */
+  uint64_t retried;     /* failed range calls that were issued again            */
+} qtn_range_stats;
+
+/*
+ * Contracts [0, 2^k) as ranges [j R, min((j+1) R, 2^k)) with R = range_slices,
+ * one qtn_contract call per range on `stream`, and writes the amplitude
+ * partial of every bitstring to out[0..n_bitstrings).  A range whose call
+ * fails is issued again after the pass, up to max_retries more passes
+ * (QTN_ETIMEOUT stops at once, its work may be in flight).  The range partials
+ * are combined with qtn_partial_combine in ascending range order, so the
+ * result is bit-identical whichever ranges were re-issued or resumed.
+ * checkpoint: NULL, or a file path.  Its first line identifies the plan
+ * (qtn_plan_fingerprint), the range size, n_bitstrings and k; every further
+ * line is one completed range as JSON, {"lo": L, "hi": H, "p": [...]}, with
+ * the four doubles of each bitstring's partial in C99 hexadecimal notation
+ * (exact).  Ranges already in the file are not contracted again; every
+ * completed range is appended and flushed to disk at once.  A torn last line
+ * is dropped.  A file of another plan or range size gives QTN_EINVAL.  When
+ * ranges are still missing after the retries, the call returns the last
+ * range's error and leaves `out` unwritten; the checkpoint keeps the rest.
+ */
+int qtn_contract_ranges(qtn_plan_t *plan, uint64_t range_slices, int32_t max_retries,
+                        const char *checkpoint, void *stream, qtn_partial *out,
+                        qtn_range_stats *stats);
+
+/* 64-bit FNV-1a fingerprint of what fixes a plan's slices and amplitudes
+ * (graph, p, angles, bitstrings, cut set, precision form); the checkpoint
+ * header carries it.  Host only. */
+int qtn_plan_fingerprint(const qtn_plan_t *plan, uint64_t *fingerprint);
+
+/* Test hook: the next `count` range calls of qtn_contract_ranges that start
+ * at slice `slice_lo` fail with QTN_EHIP without any device work (a lost range
+ * forced from the host).  count = 0 clears it.  Host only. */
+int qtn_plan_inject_faults(qtn_plan_t *plan, uint64_t slice_lo, int32_t count);
+
+/* Error-free combination of two partials (TwoSum on each component): the
+ * sum of the contraction results of two disjoint slice ranges, Eq. (2) and
+ * the master-side sum of Sec. III A.  Combining range partials in ascending
+ * order of their first slice gives a bit-reproducible amplitude.  Host only;
+ * out may alias a or b. */
 int qtn_partial_combine(const qtn_partial *a, const qtn_partial *b,
                         qtn_partial *out);
 

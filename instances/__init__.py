@@ -7,7 +7,7 @@ discarded (Sec. IV A); the angle and bitstring distributions below are this
 project's recipe for the same kind of workload.
 """
 from .generate import (Instance, random_regular_graph, make_instance,
-                       WORKLOADS, workload_instance, to_json, from_json)
+                       WORKLOADS, workload_instance, search_params, to_json, from_json)
 
 __all__ = ["Instance", "random_regular_graph", "make_instance", "WORKLOADS",
-           "workload_instance", "to_json", "from_json"]
+           "workload_instance", "search_params", "to_json", "from_json"]

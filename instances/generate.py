@@ -97,10 +97,20 @@ WORKLOADS = {
     "qaoa_n40_p2_b32_k8": dict(n=40, p=2, n_bitstrings=32, k=8, max_rank=18,
                                precision="fp32"),
     "qaoa_n80_p2_k16": dict(n=80, p=2, n_bitstrings=1, k=16, max_rank=24,
-                            precision="fp32"),
+                            precision="fp32", ga_pop=32, ga_iters=20),
     "qaoa_n120_p1_b8": dict(n=120, p=1, n_bitstrings=8, k=None, max_rank=26,
                             precision="fp32"),
+    # the same 120-qubit instance with 16 cut variables: 65,536 slices per
+    # amplitude, the binary count of the paper's 4^8 subgraphs (Sec. IV A)
+    "qaoa_n120_p1_b8_k16": dict(n=120, p=1, n_bitstrings=8, k=16, max_rank=26,
+                                precision="fp32"),
 }
+
+
+def search_params(name: str) -> dict:
+    """Cut-search parameters of a workload (Algorithm 1's N and T)."""
+    w = WORKLOADS[name]
+    return {"ga_pop": w.get("ga_pop", 11), "ga_iters": w.get("ga_iters", 4)}
 
 
 def workload_instance(name: str, seed: int = 0) -> Instance:

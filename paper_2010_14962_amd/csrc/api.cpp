@@ -2,6 +2,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <set>
 #include <stdexcept>
@@ -32,6 +33,10 @@ extern "C" void qtn_plan_opts_default(qtn_plan_opts *o) {
   o->precision = QTN_FP64;
   o->fuse_chains = 1;
   o->exec_mode = -1;
+  o->use_cost_model = 0;
+  o->offspring_factor = 16;
+  o->cost_model = nullptr;
+  o->density_matrix = 0;
 }
 
 static int fail(int code, const std::string &msg) {
@@ -109,21 +114,61 @@ extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
         return fail(QTN_EINVAL, "repeated cut variable");
       }
       P->cut.assign(cs.begin(), cs.end());
-    } else if (opts.k >= 0) {
-      if (opts.k > V) {
-        delete P;
-        return fail(QTN_EINVAL, "k > n*p");
-      }
-      P->cut = ga_cut_search(adj, opts.k, opts.ga_pop, opts.ga_iters, opts.seed).cut;
     } else {
+      // Cut search of size k: Algorithm 1 (Sec. III B) with exact fitness, or
+      // with use_cost_model the same operators with offspring ranked by the
+      // learned model and only the best ones scored exactly; either way the
+      // returned set carries its exact (width, work) from min-fill on G - C.
+      int search_rc = QTN_OK;
+      auto search = [&](int k) {
+        CutResult r;
+        if (!opts.use_cost_model || k == 0) return ga_cut_search(adj, k, opts.ga_pop, opts.ga_iters, opts.seed);
+        std::vector<uint32_t> c(k);
+        qtn_search_stats st;
+        search_rc = qtn_cut_search(graph, p, (uint32_t)k, opts.ga_pop, opts.ga_iters, opts.seed,
+                                   opts.cost_model, opts.offspring_factor, c.data(), &st);
+        if (search_rc != QTN_OK) return r;
+        r.cut.assign(c.begin(), c.end());
+        std::sort(r.cut.begin(), r.cut.end());
+        const EliminationResult e = min_fill(adj, r.cut);  // exact re-score
+        r.width = e.width;
+        r.work = e.work;
+        r.evals = st.exact_evals;
+        return r;
+      };
+      if (opts.use_cost_model && !opts.cost_model) {
+        delete P;
+        return fail(QTN_EINVAL, "use_cost_model needs a cost_model");
+      }
+      if (opts.use_cost_model && opts.offspring_factor < 1) {
+        delete P;
+        return fail(QTN_EINVAL, "offspring_factor must be >= 1");
+      }
       bool found = false;
-      for (int k = 0; k <= std::min(opts.k_max, V); ++k) {
-        CutResult r = ga_cut_search(adj, k, opts.ga_pop, opts.ga_iters, opts.seed);
-        if (opts.max_rank <= 0 || r.width <= opts.max_rank) {
-          P->cut = r.cut;
-          found = true;
-          break;
+      if (opts.k >= 0) {
+        if (opts.k > V || (opts.use_cost_model && opts.k == V)) {
+          delete P;
+          return fail(QTN_EINVAL, opts.k > V ? "k > n*p" : "use_cost_model needs k < n*p");
         }
+        P->cut = search(opts.k).cut;
+        found = true;
+      } else {
+        for (int k = 0; k <= std::min(opts.k_max, opts.use_cost_model ? V - 1 : V); ++k) {
+          CutResult r = search(k);
+          if (search_rc != QTN_OK) break;
+          // density-matrix form: a pair width w means binary ranks up to 2 w
+          const int rank = opts.density_matrix ? 2 * r.width : r.width;
+          if (opts.max_rank <= 0 || rank <= opts.max_rank) {
+            P->cut = r.cut;
+            found = true;
+            break;
+          }
+        }
+      }
+      if (search_rc != QTN_OK) {
+        const std::string m = g_err;
+        delete P;
+        return fail(search_rc, "cut search: " + m);
       }
       if (!found) {
         delete P;
@@ -140,6 +185,28 @@ extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
     P->order = er.order;
     P->mf_width = er.width;
     P->work = er.work;
+    if (opts.density_matrix) {
+      // Sec. II A, Sec. III A: every 4-valued edge of the density-matrix
+      // network is the pair (v, v + n p) of a ket variable and its bra copy.
+      // The search and the order above ran on the graph of those pairs; a
+      // cut edge fixes both variables of its pair (4 slices per cut) and the
+      // two variables of a pair are eliminated one after the other.
+      if (2 * P->cut.size() > 30) {
+        delete P;
+        return fail(QTN_EINVAL, "at most 15 density-matrix cuts");
+      }
+      net.dm = true;
+      build_network(net);
+      std::vector<int> cut2(P->cut);
+      for (int c : P->cut) cut2.push_back(c + V);
+      P->cut = cut2;
+      std::vector<int> ord;
+      for (int v : er.order) {
+        ord.push_back(v);
+        ord.push_back(v + V);
+      }
+      P->order = ord;
+    }
     P->precision = opts.precision;
     P->popts.precision = opts.precision;
     P->popts.fuse_chains = opts.fuse_chains != 0;
@@ -211,6 +278,7 @@ extern "C" int qtn_plan_query(const qtn_plan_t *P, qtn_plan_info *info) {
   info->n_launches_wide = (int32_t)P->exec[MODE_WIDE].launches.size();
   info->slice_lds_bytes = P->exec[MODE_SLICE].lds_bytes;
   info->slice_scratch_bytes = (double)P->exec[MODE_SLICE].scratch_per_wg;
+  info->mf_width = P->mf_width;
   return QTN_OK;
 }
 

@@ -34,4 +34,8 @@ struct qtn_plan_s {
   int exec_mode = -1;      // -1 chosen per binding, else qtn::ExecMode
   qtn::ExecPlan exec[2];   // MODE_WIDE, MODE_SLICE
   qtn::DeviceState *dev = nullptr;
+  // a fault forced from the host for tests of re-issue: the next fault_count
+  // range calls of qtn_contract_ranges that start at fault_lo fail
+  uint64_t fault_lo = 0;
+  int32_t fault_count = 0;
 };

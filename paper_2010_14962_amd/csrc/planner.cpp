@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <functional>
 #include <map>
 #include <set>
@@ -25,7 +26,7 @@ void build_network(Network &net) {
   auto var = [n](uint32_t q, uint32_t l) { return (int)(l * n + q); };
   for (uint32_t l = 0; l < p; ++l) {
     for (auto &e : net.edges) {
-      Factor f{2, {var(e.first, l), var(e.second, l)}, 0, (int)l, -1};
+      Factor f{2, {var(e.first, l), var(e.second, l), -1, -1}, 0, (int)l, -1};
       std::vector<cd> v(4);
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) {
@@ -42,7 +43,7 @@ void build_network(Network &net) {
   for (uint32_t l = 0; l + 1 < p; ++l) {
     double m = std::max(std::fabs(std::cos(net.beta[l])), std::fabs(std::sin(net.beta[l])));
     for (uint32_t q = 0; q < n; ++q) {
-      Factor f{2, {var(q, l + 1), var(q, l)}, 1, (int)l, (int)q};
+      Factor f{2, {var(q, l + 1), var(q, l), -1, -1}, 1, (int)l, (int)q};
       std::vector<cd> v(4);
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) v[a * 2 + b] = rx(net.beta[l], a, b) / m;
@@ -55,7 +56,7 @@ void build_network(Network &net) {
     const uint32_t l = p - 1;
     double m = std::max(std::fabs(std::cos(net.beta[l])), std::fabs(std::sin(net.beta[l])));
     for (uint32_t q = 0; q < n; ++q) {
-      Factor f{1, {var(q, l), -1}, 2, (int)l, (int)q};
+      Factor f{1, {var(q, l), -1, -1, -1}, 2, (int)l, (int)q};
       std::vector<cd> v(2 * net.B);
       for (uint32_t b = 0; b < net.B; ++b) {
         int x = net.bits[(size_t)b * n + q];
@@ -67,15 +68,37 @@ void build_network(Network &net) {
     }
   }
   net.prefactor = pref;
+  if (net.dm) {
+    // Markov-Shi tensors: the factor over (ket vars, bra vars) is the ket
+    // factor times the conjugate of the same factor on the bra copies, so
+    // that the contraction is amplitude times conjugate amplitude.
+    const int V = (int)net.nv;
+    for (size_t f = 0; f < net.factors.size(); ++f) {
+      Factor &F = net.factors[f];
+      const int k = F.nv;
+      const std::vector<cd> ket = net.values[f];
+      const uint32_t nbv = F.kind == 2 ? net.B : 1;
+      std::vector<cd> v((size_t)nbv << (2 * k));
+      for (uint32_t b = 0; b < nbv; ++b)
+        for (int a = 0; a < (1 << k); ++a)
+          for (int c = 0; c < (1 << k); ++c)
+            v[((size_t)b << (2 * k)) + ((size_t)a << k) + c] = ket[(size_t)b * (1u << k) + a] *
+                                                              std::conj(ket[(size_t)b * (1u << k) + c]);
+      for (int j = 0; j < k; ++j) F.v[k + j] = F.v[j] + V;
+      F.nv = 2 * k;
+      net.values[f] = v;
+    }
+    net.nv = 2 * V;
+    net.prefactor = pref * pref;
+  }
 }
 
 std::vector<std::vector<int>> line_graph(const Network &net) {
   std::vector<std::vector<int>> adj(net.nv);
-  for (auto &f : net.factors) {
-    if (f.nv != 2) continue;
-    adj[f.v[0]].push_back(f.v[1]);
-    adj[f.v[1]].push_back(f.v[0]);
-  }
+  for (auto &f : net.factors)
+    for (int a = 0; a < f.nv; ++a)
+      for (int b = 0; b < f.nv; ++b)
+        if (a != b) adj[f.v[a]].push_back(f.v[b]);
   for (auto &a : adj) {
     std::sort(a.begin(), a.end());
     a.erase(std::unique(a.begin(), a.end()), a.end());
@@ -358,7 +381,7 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
               idx = idx * 2 + bit;
             }
             const auto &vals = net.values[f];
-            prod *= (F.kind == 2) ? vals[bi * 2 + idx] : vals[idx];
+            prod *= (F.kind == 2) ? vals[((size_t)bi << F.nv) + idx] : vals[idx];
           }
           t.values[(((size_t)bi << ns) + sv) * ((size_t)1 << r) + e] = prod;
         }
@@ -583,6 +606,109 @@ struct FirstFit {
 };
 }  // namespace
 
+// The closing chain of a schedule: the last steps each take the previous
+// step's output and gate factors only, down to the rank-0 result.  Their
+// whole effect is sum_c T[c] W(c), T the chain's first input and W the
+// product of its gate factors (each a function of some of T's variables).
+// The earliest grid-wide streaming step whose output can serve as T takes
+// the reduction as its epilogue; the chain's launches are dropped.
+static void fold_closing_chain(const Schedule &s, ExecPlan &x, const std::vector<int> &consumer) {
+  static const bool enabled = [] {
+    const char *e = std::getenv("QTN_DOT");  // tuning switch: 0 keeps the closing steps
+    return !(e && e[0] == '0');
+  }();
+  if (!enabled || s.steps.empty() || s.result < 0) return;
+  std::vector<char> in_launch(s.steps.size(), 0);
+  for (const LaunchGroup &G : x.launches)
+    if (G.kind == 1) in_launch[G.step] = 1;
+  int cur = (int)s.steps.size() - 1;
+  if (s.steps[cur].out != s.result) return;
+  std::vector<int> chain{cur};
+  int best = -1;
+  size_t best_len = 0;
+  for (;;) {
+    int prev = -1, n_nonleaf = 0;
+    for (int i : s.steps[cur].in)
+      if (!s.tensors[i].leaf) {
+        ++n_nonleaf;
+        prev = i;
+      }
+    if (n_nonleaf != 1 || consumer[prev] != cur) break;
+    const int p = s.tensors[prev].producer;
+    if (p < 0) break;
+    const Step &H = s.steps[p];
+    // the head must be a grid-wide streaming step (output of at least 2^8
+    // elements per instance, at most 4 summed and 4 varying operands)
+    int nvary = 0;
+    const uint32_t cbits = H.rC >= 32 ? ~0u : ((1u << H.rC) - 1u);
+    for (size_t i = 0; i < H.in.size(); ++i) nvary += (H.mask[i] & cbits) ? 1 : 0;
+    const bool streaming = in_launch[p] && H.rC >= 8 && H.nk <= 4 && nvary >= 1 && nvary <= 4 &&
+                           x.loc[prev] == LOC_GLOBAL;
+    if (streaming) {
+      best = p;
+      best_len = chain.size();
+    }
+    chain.push_back(p);
+    cur = p;
+  }
+  if (best < 0) return;
+  const int T = s.steps[best].out;
+  const Tensor &TT = s.tensors[T];
+  const Tensor &R = s.tensors[s.result];
+  if (TT.bdep != R.bdep || TT.sdep != R.sdep) return;
+  std::vector<int> tail(chain.begin(), chain.begin() + best_len);
+  std::vector<char> is_tail(s.steps.size(), 0);
+  for (int st : tail) is_tail[st] = 1;
+  // gate factors of the chain, as bits of T's index (first variable = top bit)
+  std::vector<int> leaves;
+  std::vector<uint32_t> masks;
+  int nmixed = 0;
+  for (int st : tail)
+    for (int i : s.steps[st].in) {
+      if (!s.tensors[i].leaf) continue;
+      uint32_t m = 0;
+      for (int v : s.tensors[i].vars) {
+        auto it = std::find(TT.vars.begin(), TT.vars.end(), v);
+        if (it == TT.vars.end()) return;   // a variable T does not carry
+        m |= 1u << (TT.rank() - 1 - (int)(it - TT.vars.begin()));
+      }
+      if ((m & 255u) && (m >> 8)) ++nmixed;
+      if (s.tensors[i].rank() > 4) return;
+      leaves.push_back(i);
+      masks.push_back(m);
+    }
+  if ((int)leaves.size() > kMaxDotLeaves || nmixed > kMaxDotMixed) return;
+  int nvals = 0;
+  for (int i : leaves) nvals += 1 << s.tensors[i].rank();
+  if (nvals > kMaxDotValues) return;
+  // every program of the chain must hold chain steps only
+  for (LaunchGroup &G : x.launches) {
+    if (G.kind != 0) continue;
+    for (int p : G.programs) {
+      int nt = 0;
+      for (int st : x.programs[p].steps) nt += is_tail[st];
+      if (nt && nt != (int)x.programs[p].steps.size()) return;
+    }
+  }
+  std::vector<LaunchGroup> kept;
+  for (LaunchGroup &G : x.launches) {
+    if (G.kind == 1) {
+      if (!is_tail[G.step]) kept.push_back(G);
+      continue;
+    }
+    LaunchGroup g = G;
+    g.programs.clear();
+    for (int p : G.programs)
+      if (!is_tail[x.programs[p].steps[0]]) g.programs.push_back(p);
+    if (!g.programs.empty()) kept.push_back(g);
+  }
+  x.launches = kept;
+  x.dot_step = best;
+  x.dot_tensor = T;
+  x.dot_leaves = leaves;
+  x.dot_masks = masks;
+}
+
 ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget) {
   const int nst = (int)s.steps.size();
   const int nt = (int)s.tensors.size();
@@ -783,6 +909,7 @@ ExecPlan build_exec(const Schedule &s, int mode, uint32_t lds_budget) {
       if (!launched[c]) tail.programs.push_back((int)c);
     if (!tail.programs.empty()) x.launches.push_back(tail);
   }
+  if (mode == MODE_WIDE) fold_closing_chain(s, x, consumer);
   for (auto &P : x.programs) {
     x.lds_bytes = std::max(x.lds_bytes, P.lds_bytes);
     x.scratch_per_wg = std::max(x.scratch_per_wg, P.scratch_bytes);
@@ -815,7 +942,7 @@ Layout layout(Schedule &s, const ExecPlan &x, uint64_t B, uint64_t S, uint64_t w
   for (size_t g = 0; g < nl; ++g)
     for (int st : lsteps[g])
       for (int i : s.steps[st].in) last_launch[i] = std::max(last_launch[i], (int)g);
-  last_launch[s.result] = (int)nl;  // read by the slice sum
+  last_launch[x.dot_step >= 0 ? x.dot_tensor : s.result] = (int)nl;  // read by the slice sum
   for (size_t g = 0; g < nl; ++g) {
     for (int st : lsteps[g]) {
       const int o = s.steps[st].out;
@@ -858,7 +985,14 @@ Layout layout(Schedule &s, const ExecPlan &x, uint64_t B, uint64_t S, uint64_t w
   }
   L.exp_bytes = eo - L.data_bytes;
   L.partial_off = eo;
-  L.scratch_off = align256(eo + B * 32);
+  uint64_t po = align256(eo + B * 32);
+  if (x.dot_step >= 0) {
+    const Tensor &T = s.tensors[x.dot_tensor];
+    L.dot_slots = (uint64_t)1 << std::max(0, s.steps[x.dot_step].rC - 8);
+    L.dot_off = po;
+    po = align256(po + instances(T, B, S) * L.dot_slots * 16);
+  }
+  L.scratch_off = po;
   L.wg_slots = wg_slots;
   L.total_bytes = align256(L.scratch_off + wg_slots * align256(x.scratch_per_wg));
   return L;
@@ -902,9 +1036,18 @@ LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, 
       for (int i : s.steps[st].in)
         if (global(i) && !made.count(i)) data(i, false, rng[g + 1]);
       if (global(s.steps[st].out)) data(s.steps[st].out, true, rng[g + 1]);
+      if (st == x.dot_step)
+        rng[g + 1].push_back({L.dot_off, L.dot_off + instances(s.tensors[x.dot_tensor], B, S) * L.dot_slots * 16,
+                              true});
     }
   }
-  data(s.result, false, rng[nl + 1]);
+  if (x.dot_step >= 0) {
+    data(x.dot_tensor, false, rng[nl + 1]);
+    rng[nl + 1].push_back({L.dot_off, L.dot_off + instances(s.tensors[x.dot_tensor], B, S) * L.dot_slots * 16,
+                           false});
+  } else {
+    data(s.result, false, rng[nl + 1]);
+  }
   rng[nl + 1].push_back({L.partial_off, L.partial_off + B * 32, true});
   if (scaled && L.exp_bytes) rng[nl + 1].push_back({L.data_bytes, L.data_bytes + L.exp_bytes, true});
 

@@ -22,10 +22,11 @@ constexpr int kMaxStreamKappa = 4; // summed variables per streaming pass
 // many blocks writing one instance do not all update one address.
 constexpr int kMaxSlots = 32;
 
-// One gate factor of the merged binary network (Sec. II A, Fig. 1).
+// One gate factor of the merged binary network (Sec. II A, Fig. 1).  In the
+// density-matrix form a factor spans the ket variables and their bra copies.
 struct Factor {
-  int nv;      // 1 or 2 variables
-  int v[2];    // variable ids, axis order of the values
+  int nv;      // 1 to 4 variables
+  int v[4];    // variable ids, axis order of the values (first = most significant)
   int kind;    // 0 ZZ, 1 RX between layers, 2 measured RX (depends on x)
   int layer;
   int qubit;   // RX / OUT qubit
@@ -33,6 +34,10 @@ struct Factor {
 
 struct Network {
   uint32_t n = 0, p = 0, nv = 0;
+  // Density-matrix form (Sec. II A): every variable v < n p has a bra copy
+  // v + n p; each gate's factor is the Markov-Shi tensor over both, the ket
+  // factor times the conjugate of its copy, and the result is |amplitude|^2.
+  bool dm = false;
   std::vector<std::pair<uint32_t, uint32_t>> edges;
   std::vector<double> gamma, beta;
   std::vector<uint8_t> bits;  // [B][n]
@@ -177,7 +182,20 @@ struct ExecPlan {
   std::vector<int> slot;        // exponent slot of LDS / scratch tensors
   uint32_t lds_bytes = 0;       // largest program LDS footprint
   uint64_t scratch_per_wg = 0;
+  // Closing chain folded into a grid-wide step (grid-wide mode): when every
+  // step after `dot_step` only sums variables of its output T against gate
+  // factors over T's variables, the rank-0 result is sum_c T[c] W(c) with W
+  // the product of those factors.  dot_step then reduces its outputs against
+  // W instead of storing T, and the closing steps are not launched.
+  int dot_step = -1;
+  int dot_tensor = -1;              // T
+  std::vector<int> dot_leaves;      // the closing chain's gate factors
+  std::vector<uint32_t> dot_masks;  // their variables as bits of T's index
 };
+
+constexpr int kMaxDotLeaves = 32;   // gate factors of a folded closing chain
+constexpr int kMaxDotMixed = 8;     // of those, with variables on both sides of bit 8
+constexpr int kMaxDotValues = 256;  // their values together (complex)
 
 // MODE_WIDE: trees of small steps become workgroup programs, the rest run as
 // grid-wide steps.  MODE_SLICE: the whole schedule is one program per
@@ -192,6 +210,8 @@ struct Layout {
   uint64_t partial_off = 0;      // running per-bitstring partials
   uint64_t scratch_off = 0;      // per-workgroup scratch region
   uint64_t wg_slots = 0;
+  uint64_t dot_off = 0;          // block partials of a folded closing chain
+  uint64_t dot_slots = 0;        // per instance of T
 };
 
 // Instance count of a tensor inside a wave.

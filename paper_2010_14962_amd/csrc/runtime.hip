@@ -15,6 +15,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -56,8 +59,36 @@ struct PStep {
   uint32_t wg_flags;      // in a workgroup program: 1 = every operand in LDS
   int tiled_fold;         // step_tiled: operand staged as complex128 times the
                           // kappa coefficient, or -1
+  uint32_t dot;           // 1: reduce the outputs against the closing chain's
+                          //    gate factors (DotArgs) instead of storing them
+  uint32_t dot_lds;       // dynamic LDS bytes of that epilogue
+  const void *dotp;       // DotArgs in device memory (set at launch)
 };
 static_assert(sizeof(PStep) % 16 == 0, "PStep layout");
+
+// Gate factors of a closing chain folded into a grid-wide step: the step
+// adds acc(c) W(c) over its outputs c, W(c) = prod_l leaf_l[pext(c, mask_l)],
+// one partial per block and instance.  Leaves are ordered: variables only in
+// the low 8 bits of c (fixed per lane), only above them (fixed per row), both.
+struct DotLeaf {
+  const double *base;     // complex128 values, interleaved re/im
+  uint64_t bstride;       // complex values between bitstrings (0: shared)
+  uint32_t selmask;       // slice bits selecting the variant
+  uint32_t mask;          // variables as bits of the step's output index
+  uint32_t rank;          // 2^rank values per variant
+  uint32_t off;           // position of its values in the staged table
+};
+static_assert(sizeof(DotLeaf) == 32, "DotLeaf layout");
+constexpr uint32_t kDotValues = kMaxDotValues;   // staged leaf values per instance
+struct DotArgs {
+  uint32_t nleaf, nlo, nhi, nmix;
+  uint32_t nvals;         // staged values (<= kDotValues)
+  uint32_t slots;         // partial slots per instance
+  double2 *part;          // [instance][slots] block partials
+  DotLeaf leaf[kMaxDotLeaves];
+  uint8_t owner[kDotValues];  // leaf of each staged value
+};
+static_assert(sizeof(DotArgs) % 16 == 0, "DotArgs layout");
 
 // One tensor a program stages in LDS at its start (as complex128):
 //  * a gate factor: the variant of instance (b, s) is
@@ -80,17 +111,29 @@ static_assert(sizeof(LeafStage) == 64, "LeafStage layout");
 // A program in device memory is one blob: its LeafStage records, then its
 // PStep descriptors.  A launch of workgroup programs names up to
 // kMaxGroupProgs of them in its arguments, so that a workgroup finds its
-// program without a memory round trip.
+// program without a memory round trip.  The programs of one launch may come
+// from different plans (several circuits in one persistent launch): each
+// carries its own blob, slice range and per-workgroup scratch.
 constexpr int kMaxGroupProgs = 32;
 constexpr int kDescChunk = 8;          // program steps resident in LDS at a time
 struct GroupArgs {
   uint32_t nprog;
-  uint32_t blob_off[kMaxGroupProgs];   // bytes from the blob base
   uint32_t item_end[kMaxGroupProgs];   // cumulative item counts
   uint16_t nsteps[kMaxGroupProgs];
   uint16_t nstage[kMaxGroupProgs];
   uint8_t bdep[kMaxGroupProgs];
   uint8_t sdep[kMaxGroupProgs];
+  uint32_t ns[kMaxGroupProgs];         // slices of the program's wave
+  const char *blob[kMaxGroupProgs];    // the program's blob
+  char *scratch[kMaxGroupProgs];       // its plan's per-workgroup scratch region
+  uint64_t scratch_stride[kMaxGroupProgs];
+  uint64_t s_lo[kMaxGroupProgs];       // first slice of the program's wave
+};
+
+// Launch configuration of a grid-wide streaming step.
+struct StepTune {
+  uint32_t target = 1024;   // blocks over the chip
+  bool stream_only = false; // run step_stream even where step_tiled applies
 };
 
 struct DeviceState {
@@ -121,9 +164,15 @@ struct DeviceState {
     double ms = 0, bytes = 0, flops = 0;
   };
   std::vector<StepTiming> t_step;  // per schedule step
+  StepTiming t_prog;               // launches of workgroup programs
   uint64_t t_launches = 0, t_failed = 0;
   int t_last_error = 0;
   std::vector<double> step_bytes, step_flops;  // per instance of each step
+  // per item of each workgroup program: bytes of the tensors it reads or
+  // writes outside LDS (gate factors, workspace, scratch) and flops of its steps
+  std::vector<double> prog_bytes, prog_flops;
+  uint64_t dot_args_off = 0;      // DotArgs of a folded closing chain in the blob
+  std::vector<StepTune> tune;     // launch configuration per step (qtn_plan_autotune)
   // independent launch units run on side streams (default priority),
   // ordered by events after their dependencies
   LaunchGraph lg;
@@ -220,6 +269,41 @@ __device__ __forceinline__ uint64_t enc_c64e(double2 v) {
          (uint64_t)((uint32_t)mi & 0xFFFFFFFu);
 }
 
+// The rescaled store of a grid-wide step: v * 2^-sh stored in the tensor's
+// form.  For the 64-bit form the shift only changes the stored exponent (the
+// mantissas are those of v), so no scaling pass over the values is needed.
+// Returns the float exponent field of the stored value's larger part (the
+// per-instance maximum that consumers shift by).
+__device__ __forceinline__ uint32_t store_scaled(void *base, uint32_t f64, uint64_t i, double2 v, int sh) {
+  if (f64) {
+    v.x = ldexp(v.x, -sh);
+    v.y = ldexp(v.y, -sh);
+    ((double2 *)base)[i] = v;
+    const float ax = (float)fabs(v.x), ay = (float)fabs(v.y);
+    return max(__float_as_uint(ax), __float_as_uint(ay)) & 0x7F800000u;
+  }
+  const double m = fmax(fabs(v.x), fabs(v.y));
+  uint64_t w = 0ull;
+  uint32_t mb = 0u;
+  if (m > 0.0) {
+    // frexp exponent of m from its bits (m is normal: |v| of the steps is far
+    // above 2^-1022)
+    const int e = (int)((__double_as_longlong(m) >> 52) & 0x7ff) - 1022;
+    const int es = e - sh;   // exponent of the stored value
+    const int E = es + 127;
+    if (E >= 1) {
+      const int lim = 134217727;  // 2^27 - 1
+      const int mr = min(max(__double2int_rn(ldexp(v.x, 27 - e)), -lim), lim);
+      const int mi = min(max(__double2int_rn(ldexp(v.y, 27 - e)), -lim), lim);
+      w = ((uint64_t)min(E, 255) << 56) | ((uint64_t)((uint32_t)mr & 0xFFFFFFFu) << 28) |
+          (uint64_t)((uint32_t)mi & 0xFFFFFFFu);
+      mb = (uint32_t)min(max(es + 126, 0), 255) << 23;
+    }
+  }
+  ((uint64_t *)base)[i] = w;
+  return mb;
+}
+
 __device__ __forceinline__ double2 dec_c64e(uint64_t w) {
   const int re = ((int)((uint32_t)(w >> 28) << 4)) >> 4;
   const int im = ((int)((uint32_t)w << 4)) >> 4;
@@ -302,6 +386,95 @@ __device__ __forceinline__ uint32_t cpart(const OpDesc &o, uint32_t c, int rC) {
 }
 __device__ __forceinline__ uint32_t kpart(const OpDesc &o, uint32_t kap, int rC) {
   return rC >= 32 ? 0u : (dpext(kap, o.mask >> rC) << __popc(o.mask & out_bits(rC)));
+}
+
+// ---------------------------------------------------------------------------
+// Folded closing chain: the epilogue of a grid-wide step that adds acc(c) W(c)
+// over its outputs c instead of storing them (see DotArgs).  LDS (dynamic,
+// after the step's own): staged factor values | 32 row products | 4 sums.
+// ---------------------------------------------------------------------------
+struct DotState {
+  double2 wl;                 // product of the lane-only factors at this lane
+  uint32_t li[kMaxDotMixed];  // lane part of each mixed factor's index
+  double2 acc;                // this thread's sum of acc(c) W(c)
+};
+
+// Copies the DotArgs record into LDS (once per block); every thread calls it.
+__device__ void dot_args_to_lds(const DotArgs *src, DotArgs *dst) {
+  const uint32_t *s = (const uint32_t *)src;
+  uint32_t *d = (uint32_t *)dst;
+  for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(DotArgs) / 4); i += blockDim.x) d[i] = s[i];
+  __syncthreads();
+}
+
+// Stages the factor values of instance (b, s) and sets this lane's parts.
+// A is the LDS copy of the record.  Every thread of the block calls it.
+__device__ void dot_begin(const DotArgs *A, uint32_t b, uint32_t s, double2 *sv, DotState &D) {
+  const uint32_t t = threadIdx.x;
+  const uint32_t nvals = A->nvals, nlo = A->nlo, nmix = A->nmix;
+  __syncthreads();  // the previous instance is done with the table
+  if (t < nvals) {
+    const DotLeaf &L = A->leaf[A->owner[t]];
+    const uint64_t o = (uint64_t)b * L.bstride + ((uint64_t)dpext(s, L.selmask) << L.rank) + (t - L.off);
+    sv[t] = make_double2(L.base[2 * o], L.base[2 * o + 1]);
+  }
+  __syncthreads();
+  D.wl = make_double2(1.0, 0.0);
+  for (uint32_t l = 0; l < nlo; ++l) D.wl = cmul(D.wl, sv[A->leaf[l].off + dpext(t, A->leaf[l].mask)]);
+#pragma unroll
+  for (uint32_t j = 0; j < (uint32_t)kMaxDotMixed; ++j)
+    D.li[j] = j < nmix ? dpext(t, A->leaf[nlo + A->nhi + j].mask & 255u) : 0u;
+  D.acc = make_double2(0.0, 0.0);
+}
+
+// Products of the row-only factors for rows row0 .. row0 + n - 1 (n <= 32).
+// Every thread of the block calls it.
+__device__ void dot_rows(const DotArgs *A, const double2 *sv, uint32_t row0, uint32_t n, double2 *sw) {
+  __syncthreads();  // readers of the previous rows' products are done
+  const uint32_t t = threadIdx.x;
+  if (t < n) {
+    const uint32_t row = row0 + t;
+    double2 w = make_double2(1.0, 0.0);
+    for (uint32_t l = A->nlo; l < A->nlo + A->nhi; ++l) w = cmul(w, sv[A->leaf[l].off + dpext(row, A->leaf[l].mask >> 8)]);
+    sw[t] = w;
+  }
+  __syncthreads();
+}
+
+// Adds v W(c) / wl for the output c = row:lane, wrow being the row's
+// product: the lane-only factor wl is applied once, in dot_end.
+__device__ __forceinline__ void dot_add(const DotArgs *A, const double2 *sv, DotState &D, double2 wrow,
+                                        uint32_t row, double2 v) {
+  const uint32_t nmix = A->nmix, m0 = A->nlo + A->nhi;
+  double2 w = wrow;
+#pragma unroll
+  for (uint32_t j = 0; j < (uint32_t)kMaxDotMixed; ++j)
+    if (j < nmix) {
+      const DotLeaf &L = A->leaf[m0 + j];
+      w = cmul(w, sv[L.off + (D.li[j] | (dpext(row, L.mask >> 8) << __popc(L.mask & 255u)))]);
+    }
+  D.acc = cfma(v, w, D.acc);
+}
+
+// Block sum in a fixed order to part[qo * slots + slot].  Every thread calls it.
+__device__ void dot_end(const DotArgs *A, DotState &D, uint64_t qo, uint32_t slot, double2 *red) {
+  double2 v = cmul(D.acc, D.wl);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v.x += __shfl_xor(v.x, o, 64);
+    v.y += __shfl_xor(v.y, o, 64);
+  }
+  if ((threadIdx.x & 63u) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 r = red[0];
+    for (int w = 1; w < 4; ++w) {
+      r.x += red[w].x;
+      r.y += red[w].y;
+    }
+    A->part[qo * A->slots + slot] = r;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
@@ -626,10 +799,7 @@ __device__ __forceinline__ void copy_to_lds(QTN_LDS char *dst, const char *__res
 // runs the steps, kDescChunk descriptors at a time.  Items never wait on
 // each other.
 template <bool SCALE>
-__global__ __launch_bounds__(256) void wg_programs(const char *__restrict__ blobs, const GroupArgs ga,
-                                                   uint32_t nbits, uint32_t total, uint64_t s_lo,
-                                                   uint32_t ns_wave, char *scratch,
-                                                   uint64_t scratch_per_wg, uint32_t lds_bytes,
+__global__ __launch_bounds__(256) void wg_programs(const GroupArgs ga, uint32_t total, uint32_t lds_bytes,
                                                    int max_slots, uint32_t desc_off) {
   char *smem = wg_smem;
   WgCtx W;
@@ -639,18 +809,17 @@ __global__ __launch_bounds__(256) void wg_programs(const char *__restrict__ blob
   W.sE = (QTN_LDS int *)(sm + lds_bytes + 256 * 16);
   W.sM = (QTN_LDS uint32_t *)(W.sE + max_slots);
   W.red4 = W.sM + max_slots;
-  W.scratch = scratch + (uint64_t)blockIdx.x * scratch_per_wg;
   QTN_LDS char *desc = sm + desc_off;
-  (void)nbits;
   for (uint32_t item = blockIdx.x; item < total; item += gridDim.x) {
     uint32_t j = 0;
     while (j + 1 < ga.nprog && item >= ga.item_end[j]) ++j;
     const uint32_t q = item - (j ? ga.item_end[j - 1] : 0u);
-    const uint32_t ns = ga.sdep[j] ? ns_wave : 1u;
+    const uint32_t ns = ga.sdep[j] ? ga.ns[j] : 1u;
     const uint32_t b = q / ns;
     const uint32_t sl = q - b * ns;
-    const uint32_t s = (uint32_t)(s_lo + sl);
-    const char *blob = blobs + ga.blob_off[j];
+    const uint32_t s = (uint32_t)(ga.s_lo[j] + sl);
+    W.scratch = ga.scratch[j] + (uint64_t)blockIdx.x * ga.scratch_stride[j];
+    const char *blob = ga.blob[j];
     const uint32_t nst = ga.nsteps[j], nstg = ga.nstage[j];
     const uint32_t lsb = nstg * (uint32_t)sizeof(LeafStage);
     __syncthreads();  // the previous item is done with the LDS
@@ -752,9 +921,20 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
   const uint32_t nC = 1u << d.rC;
   // work units of the instance: jspan x 256 consecutive elements
   const uint32_t units = (nC >> 8) / jspan;
+  extern __shared__ __align__(16) char dsm[];
+  const bool dot = d.dot != 0;
+  DotArgs *DA = (DotArgs *)dsm;
+  double2 *dsv = (double2 *)(dsm + sizeof(DotArgs));
+  if (dot) dot_args_to_lds((const DotArgs *)d.dotp, DA);
+  double2 *dsw = dot ? dsv + DA->nvals : nullptr;
+  DotState DS;
   for (uint64_t q = blockIdx.y; q < Q; q += gridDim.y) {
     InstanceSetup I;
     setup_instance<SCALE>(d, ns, q, s_lo, I);
+    if (dot) {
+      const uint32_t b = (uint32_t)(q / ns);
+      dot_begin(DA, b, (uint32_t)(s_lo + (q - (uint64_t)b * ns)), dsv, DS);
+    }
     __syncthreads();
     if (t < NKAP) {
       double2 c = make_double2(1.0, 0.0);
@@ -775,6 +955,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
     uint32_t wmax = 0;
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
       const uint32_t j0 = u * jspan;            // in units of 256 elements
+      if (dot) dot_rows(DA, dsv, j0, jspan, dsw);
       uint32_t hoff[NV];
 #pragma unroll 1
       for (uint32_t jj = 0; jj < jspan; ++jj) {
@@ -821,15 +1002,23 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
             acc.y += prod.y;
           }
         }
-        if (SCALE) {
-          acc.x = ldexp(acc.x, -sh);
-          acc.y = ldexp(acc.y, -sh);
-          wmax = max(wmax, max_bits(acc, of));
+        if (dot) {
+          if (SCALE) {
+            acc.x = ldexp(acc.x, -sh);
+            acc.y = ldexp(acc.y, -sh);
+          }
+          dot_add(DA, dsv, DS, dsw[jj], j0 + jj, acc);
+        } else if (SCALE) {
+          wmax = max(wmax, store_scaled(op, of, c, acc, sh));
+        } else {
+          store_g(op, of, c, acc);
         }
-        store_g(op, of, c, acc);
       }
     }
-    if (SCALE) {
+    if (dot) {
+      dot_end(DA, DS, I.qo, blockIdx.x, dsw + 32);
+      if (SCALE && t == 0 && blockIdx.x == 0) d.out.E[I.qo] = I.esum;
+    } else if (SCALE) {
       // every thread of the block ran the same trips
       const uint32_t m = block_max(wmax, red4);
       if (t == 0) {
@@ -894,9 +1083,19 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
   const uint64_t Q = (uint64_t)nb * ns;
   const uint32_t rows = (1u << d.rC) >> 8;
   const uint32_t units = rows / jspan;
+  const bool dot = d.dot != 0;
+  DotArgs *DA = (DotArgs *)(stage + d.tiled_lds);
+  double2 *dsv = (double2 *)(stage + d.tiled_lds + sizeof(DotArgs));
+  if (dot) dot_args_to_lds((const DotArgs *)d.dotp, DA);
+  double2 *dsw = dot ? dsv + DA->nvals : nullptr;
+  DotState DS;
   for (uint64_t q = blockIdx.y; q < Q; q += gridDim.y) {
     InstanceSetup I;
     setup_instance<SCALE>(d, ns, q, s_lo, I);
+    if (dot) {
+      const uint32_t b = (uint32_t)(q / ns);
+      dot_begin(DA, b, (uint32_t)(s_lo + (q - (uint64_t)b * ns)), dsv, DS);
+    }
     __syncthreads();
     if (t < NKAP) {
       double2 c = make_double2(1.0, 0.0);
@@ -937,6 +1136,7 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
       return cfma(head(k, v), opnd(v, k), acc);
     };
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+      if (dot) dot_rows(DA, dsv, u * jspan, jspan, dsw);
       // operand bases of the current chunk of 16 rows: instance offset plus
       // the index part of the row bits above the lowest four
       const char *cbase[NV];
@@ -1006,15 +1206,23 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
 #pragma unroll 4
           for (uint32_t k = 0; k < NKAP; ++k) acc = mac(k, NV - 1, acc);
         }
-        if (SCALE) {
-          acc.x = ldexp(acc.x, -sh);
-          acc.y = ldexp(acc.y, -sh);
-          wmax = max(wmax, max_bits(acc, of));
+        if (dot) {
+          if (SCALE) {
+            acc.x = ldexp(acc.x, -sh);
+            acc.y = ldexp(acc.y, -sh);
+          }
+          dot_add(DA, dsv, DS, dsw[jj], row, acc);
+        } else if (SCALE) {
+          wmax = max(wmax, store_scaled(op, of, ((uint64_t)row << 8) | t, acc, sh));
+        } else {
+          store_g(op, of, ((uint64_t)row << 8) | t, acc);
         }
-        store_g(op, of, ((uint64_t)row << 8) | t, acc);
       }
     }
-    if (SCALE) {
+    if (dot) {
+      dot_end(DA, DS, I.qo, blockIdx.x, dsw + 32);
+      if (SCALE && t == 0 && blockIdx.x == 0) d.out.E[I.qo] = I.esum;
+    } else if (SCALE) {
       const uint32_t m = block_max(wmax, red4);
       if (t == 0) {
         raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots + (blockIdx.x % kMaxSlots), m);
@@ -1078,14 +1286,13 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
                                                  uint32_t count, double pref,
                                                  qtn_partial *partials, int init,
                                                  qtn_partial *host_out, uint32_t *clear,
-                                                 uint64_t nclear, uint64_t keep_lo, uint64_t keep_hi) {
+                                                 uint64_t nclear, uint64_t keep_lo, uint64_t keep_hi,
+                                                 const double2 *dotp, uint64_t dstride, uint32_t dslots) {
   __shared__ double sre[256], cre[256], sim[256], cim[256];
   const uint32_t b = blockIdx.x;
   const uint32_t t = threadIdx.x;
   double ar = 0, cr = 0, ai = 0, ci = 0;
-  for (uint32_t sl = t; sl < count; sl += 256) {
-    const uint64_t at = (uint64_t)b * bstride + (uint64_t)sl * sstride;
-    const double2 v = load_g(res, res64, at);
+  auto accumulate = [&](double2 v, uint64_t at) {
     double vr = v.x, vi = v.y;
     if (SCALE) {
       const int e = E[at];
@@ -1101,6 +1308,48 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
     two_sum(ai, vi, s, e2);
     ai = s;
     ci += e2;
+  };
+  if (dotp && dslots > 16) {
+    // many block partials per instance (few instances): the block sums each
+    // instance's partials together, in a fixed tree order
+    for (uint32_t sl = 0; sl < count; ++sl) {
+      const uint64_t at = (uint64_t)b * bstride + (uint64_t)sl * sstride;
+      double2 v = make_double2(0.0, 0.0);
+      for (uint32_t j = t; j < dslots; j += 256) {
+        const double2 w = dotp[at * dstride + j];
+        v.x += w.x;
+        v.y += w.y;
+      }
+      sre[t] = v.x;
+      sim[t] = v.y;
+      __syncthreads();
+      for (uint32_t h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+          sre[t] += sre[t + h];
+          sim[t] += sim[t + h];
+        }
+        __syncthreads();
+      }
+      if (t == 0) accumulate(make_double2(sre[0], sim[0]), at);
+      __syncthreads();
+    }
+  } else {
+    for (uint32_t sl = t; sl < count; sl += 256) {
+      const uint64_t at = (uint64_t)b * bstride + (uint64_t)sl * sstride;
+      double2 v;
+      if (dotp) {
+        // block partials of a folded closing chain, summed in slot order
+        v = make_double2(0.0, 0.0);
+        for (uint32_t j = 0; j < dslots; ++j) {
+          const double2 w = dotp[at * dstride + j];
+          v.x += w.x;
+          v.y += w.y;
+        }
+      } else {
+        v = load_g(res, res64, at);
+      }
+      accumulate(v, at);
+    }
   }
   sre[t] = ar;
   cre[t] = cr;
@@ -1211,19 +1460,18 @@ using namespace qtn;
 
 static uint32_t tiled_lds_bytes(const PStep &d);
 
-extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t bytes,
-                                       uint64_t S) {
-  set_error("");
-  if (!P || !dev_ptr) {
-    set_error("NULL argument");
-    return QTN_EINVAL;
-  }
+// Layout and LDS sizes of a binding with S slices per wave (host only).
+struct BindShape {
+  uint64_t S = 1;
+  int mode = MODE_WIDE;
+  Layout L;
+  int max_slots = 1;
+  uint32_t lds_bytes = 0, desc_off = 0, lds_total = 0;
+};
+
+static int bind_shape(qtn_plan_t *P, uint64_t S, BindShape &B_) {
   if (S == 0 || S > (1ull << 24)) {
     set_error("slices_per_wave must be in [1, 2^24]");
-    return QTN_EINVAL;
-  }
-  if (((uintptr_t)dev_ptr) & 255u) {
-    set_error("workspace must be 256-byte aligned");
     return QTN_EINVAL;
   }
   const uint64_t maxS = P->cut.empty() ? 1 : (1ull << P->cut.size());
@@ -1231,16 +1479,11 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   Schedule &sch = P->sched;
   const int mode = choose_mode(P, S);
   const ExecPlan &X = P->exec[mode];
-  Layout L;
   try {
-    L = layout(sch, X, P->net.B, S, wg_slots_for(P, mode, S));
+    B_.L = layout(sch, X, P->net.B, S, wg_slots_for(P, mode, S));
   } catch (const std::exception &e) {
     set_error(e.what());
     return QTN_ESTATE;
-  }
-  if (bytes < L.total_bytes) {
-    set_error("workspace too small: need " + std::to_string(L.total_bytes) + " bytes");
-    return QTN_ENOMEM;
   }
   if (!P->cut.empty() && !sch.tensors[sch.result].sdep) {
     set_error("internal: sliced result does not depend on the slice");
@@ -1261,79 +1504,56 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     set_error("program LDS footprint too large");
     return QTN_ESTATE;
   }
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  DeviceState *D = P->dev;
-  if (!D || D->device != dev) {
-    device_state_free(D);
-    D = new DeviceState();
-    P->dev = D;
-    D->device = dev;
-    // gate factors stay complex128 in every precision form
-    D->leaf_elem_off.assign(sch.tensors.size(), 0);
-    uint64_t nleaf = 0;
-    for (size_t t = 0; t < sch.tensors.size(); ++t)
-      if (sch.tensors[t].leaf) {
-        D->leaf_elem_off[t] = nleaf;
-        nleaf += sch.tensors[t].values.size();
-      }
-    std::vector<double> host(std::max<uint64_t>(nleaf, 1) * 2, 0.0);
-    for (size_t t = 0; t < sch.tensors.size(); ++t) {
-      const Tensor &T = sch.tensors[t];
-      if (!T.leaf) continue;
-      for (size_t i = 0; i < T.values.size(); ++i) {
-        const uint64_t k = D->leaf_elem_off[t] + i;
-        host[2 * k] = T.values[i].real();
-        host[2 * k + 1] = T.values[i].imag();
-      }
+  B_.S = S;
+  B_.mode = mode;
+  B_.max_slots = max_slots;
+  B_.lds_bytes = lds_bytes;
+  B_.desc_off = desc_off;
+  B_.lds_total = lds_total;
+  return QTN_OK;
+}
+
+// Gate factors (complex128 in every precision form) as one interleaved
+// re/im array, and the element offset of each leaf tensor in it.
+static std::vector<double> leaf_host(const qtn_plan_t *P, std::vector<uint64_t> &leaf_elem_off) {
+  const Schedule &sch = P->sched;
+  leaf_elem_off.assign(sch.tensors.size(), 0);
+  uint64_t nleaf = 0;
+  for (size_t t = 0; t < sch.tensors.size(); ++t)
+    if (sch.tensors[t].leaf) {
+      leaf_elem_off[t] = nleaf;
+      nleaf += sch.tensors[t].values.size();
     }
-    double *lb = nullptr;
-    if (int rc = upload(&lb, host, "hipMalloc(leaves)")) return rc;
-    D->leafbuf = lb;
-    // pinned host memory the slice sum writes the final partials to
-    HIP_TRY(hipHostMalloc((void **)&D->host_partials, std::max<uint64_t>(P->net.B, 1) * sizeof(qtn_partial),
-                          hipHostMallocMapped));
-    HIP_TRY(hipHostGetDevicePointer((void **)&D->host_partials_dev, D->host_partials, 0));
+  std::vector<double> host(std::max<uint64_t>(nleaf, 1) * 2, 0.0);
+  for (size_t t = 0; t < sch.tensors.size(); ++t) {
+    const Tensor &T = sch.tensors[t];
+    if (!T.leaf) continue;
+    for (size_t i = 0; i < T.values.size(); ++i) {
+      const uint64_t k = leaf_elem_off[t] + i;
+      host[2 * k] = T.values[i].real();
+      host[2 * k + 1] = T.values[i].imag();
+    }
   }
+  return host;
+}
+
+static int set_program_lds(uint32_t lds_total) {
   if (lds_total > 64 * 1024) {
     HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<true>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
     HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
   }
-  LaunchGraph lg;
-  try {
-    static const int env_streams = [] {
-      const char *e = std::getenv("QTN_STREAMS");  // tuning switch: 1 serialises every launch
-      return e ? std::max(1, std::min(1 + DeviceState::kSide, std::atoi(e))) : 1 + DeviceState::kSide;
-    }();
-    lg = launch_graph(sch, X, L, P->net.B, L.S, P->precision != QTN_FP64, env_streams);
-  } catch (const std::exception &e) {
-    set_error(e.what());
-    return QTN_ESTATE;
-  }
-  for (int k = 0; k + 1 < lg.nstreams; ++k) {
-    if (!D->side[k]) HIP_TRY(hipStreamCreateWithFlags(&D->side[k], hipStreamNonBlocking));
-    if (!D->join_ev[k]) HIP_TRY(hipEventCreateWithFlags(&D->join_ev[k], hipEventDisableTiming));
-  }
-  if (!D->fork_ev) HIP_TRY(hipEventCreateWithFlags(&D->fork_ev, hipEventDisableTiming));
-  while (D->unit_ev.size() < lg.deps.size()) {
-    hipEvent_t e;
-    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    D->unit_ev.push_back(e);
-  }
-  drop_graph(D);
-  D->lg = lg;
-  D->mode = mode;
-  D->ws = (char *)dev_ptr;
-  D->ws_bytes = bytes;
-  // the exponent words start cleared; the slice sum clears them after each wave
-  if (P->precision != QTN_FP64 && L.exp_bytes) HIP_TRY(hipMemset(D->ws + L.data_bytes, 0, L.exp_bytes));
-  D->L = L;
-  D->max_slots = max_slots;
-  D->lds_bytes = lds_bytes;
-  D->lds_total = lds_total;
-  D->desc_bytes = desc_off;
+  return QTN_OK;
+}
+
+static void fill_tables(qtn_plan_t *P, DeviceState *D, const ExecPlan &X, std::vector<char> &blob);
+
+// Per-step costs, operand descriptors and program blobs of a binding whose
+// workspace (D->ws), leaf buffer (D->leafbuf) and layout (D->L) are set.
+static void fill_tables(qtn_plan_t *P, DeviceState *D, const ExecPlan &X, std::vector<char> &blob) {
+  const Schedule &sch = P->sched;
+  const uint64_t S = D->L.S;
   const uint64_t B = P->net.B;
   const bool scaled = P->precision != QTN_FP64;
   // algorithmic bytes and flops of each step, per instance
@@ -1352,6 +1572,28 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     const int nuni = (int)S_.in.size() - nvary;
     const int nprod = std::max(0, nvary - 1) + (nuni > 0 && nvary > 0 ? 1 : 0);
     D->step_flops[st] = std::ldexp(1.0, S_.nk + S_.rC) * (6.0 * nprod + (S_.nk > 0 ? 2.0 : 0.0));
+  }
+  if (X.dot_step >= 0) {
+    // the folding step reads its operands and writes no output tensor
+    const Step &H = sch.steps[X.dot_step];
+    D->step_bytes[X.dot_step] -= std::ldexp((double)elem_bytes(sch.tensors[H.out]), H.rC);
+    D->step_flops[X.dot_step] += std::ldexp(8.0, H.rC);
+  }
+  D->prog_bytes.assign(X.programs.size(), 0.0);
+  D->prog_flops.assign(X.programs.size(), 0.0);
+  for (size_t pi = 0; pi < X.programs.size(); ++pi) {
+    std::vector<char> seen(sch.tensors.size(), 0);
+    for (int st : X.programs[pi].steps) {
+      const Step &S_ = sch.steps[st];
+      D->prog_flops[pi] += D->step_flops[st];
+      std::vector<int> touched(S_.in.begin(), S_.in.end());
+      touched.push_back(S_.out);
+      for (int tid : touched) {
+        if (seen[tid] || (X.loc[tid] == LOC_LDS && !sch.tensors[tid].leaf)) continue;
+        seen[tid] = 1;
+        D->prog_bytes[pi] += std::ldexp((double)elem_bytes(sch.tensors[tid]), sch.tensors[tid].rank());
+      }
+    }
   }
   // operand descriptors
   auto describe = [&](int tid, OpDesc &o) {
@@ -1420,7 +1662,7 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     d.tiled_lds = tiled_lds_bytes(d);
   }
   // program blobs: LeafStage records, then PStep descriptors
-  std::vector<char> blob;
+  blob.clear();
   D->blob_off.assign(X.programs.size(), 0);
   for (size_t pi = 0; pi < X.programs.size(); ++pi) {
     const Program &pr = X.programs[pi];
@@ -1480,6 +1722,131 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
       blob.insert(blob.end(), pb, pb + sizeof(PStep));
     }
   }
+  // the folded closing chain: its gate factors, lane-only first, then
+  // row-only, then mixed, and the block partials' place in the workspace
+  D->dot_args_off = 0;
+  if (X.dot_step >= 0) {
+    DotArgs A;
+    std::memset(&A, 0, sizeof(A));
+    std::vector<size_t> ord;
+    for (int cls = 0; cls < 3; ++cls)
+      for (size_t j = 0; j < X.dot_leaves.size(); ++j) {
+        const uint32_t m = X.dot_masks[j];
+        const int c = (m >> 8) == 0 ? 0 : ((m & 255u) == 0 ? 1 : 2);
+        if (c == cls) ord.push_back(j);
+      }
+    uint32_t off = 0;
+    for (size_t j : ord) {
+      const uint32_t m = X.dot_masks[j];
+      const Tensor &T = sch.tensors[X.dot_leaves[j]];
+      for (uint32_t v = 0; v < (1u << T.rank()) && off + v < kDotValues; ++v) A.owner[off + v] = (uint8_t)A.nleaf;
+      DotLeaf &L = A.leaf[A.nleaf++];
+      L.base = (const double *)D->leafbuf + 2 * D->leaf_elem_off[X.dot_leaves[j]];
+      L.rank = (uint32_t)T.rank();
+      L.bstride = T.bdep ? ((uint64_t)1 << (T.rank() + __builtin_popcount(T.selmask))) : 0;
+      L.selmask = T.selmask;
+      L.mask = m;
+      L.off = off;
+      off += 1u << T.rank();
+      if ((m >> 8) == 0)
+        ++A.nlo;
+      else if ((m & 255u) == 0)
+        ++A.nhi;
+      else
+        ++A.nmix;
+    }
+    A.nvals = off;
+    A.slots = (uint32_t)D->L.dot_slots;
+    A.part = (double2 *)(D->ws + D->L.dot_off);
+    if (A.nvals > kDotValues) throw std::runtime_error("folded closing chain: too many factor values");
+    while (blob.size() % 256) blob.push_back(0);
+    D->dot_args_off = blob.size();
+    const char *pa = (const char *)&A;
+    blob.insert(blob.end(), pa, pa + sizeof(A));
+    PStep &h = D->steps[X.dot_step];
+    h.dot = 1;
+    h.dot_lds = (uint32_t)sizeof(DotArgs) + (A.nvals + 32 + 4) * 16u;
+  }
+}
+
+extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t bytes,
+                                       uint64_t S_req) {
+  set_error("");
+  if (!P || !dev_ptr) {
+    set_error("NULL argument");
+    return QTN_EINVAL;
+  }
+  if (((uintptr_t)dev_ptr) & 255u) {
+    set_error("workspace must be 256-byte aligned");
+    return QTN_EINVAL;
+  }
+  BindShape shape;
+  if (int rc = bind_shape(P, S_req, shape)) return rc;
+  const uint64_t S = shape.S;
+  const int mode = shape.mode;
+  const Layout &L = shape.L;
+  const ExecPlan &X = P->exec[mode];
+  Schedule &sch = P->sched;
+  if (bytes < L.total_bytes) {
+    set_error("workspace too small: need " + std::to_string(L.total_bytes) + " bytes");
+    return QTN_ENOMEM;
+  }
+  const int max_slots = shape.max_slots;
+  const uint32_t lds_bytes = shape.lds_bytes, desc_off = shape.desc_off, lds_total = shape.lds_total;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  DeviceState *D = P->dev;
+  if (!D || D->device != dev) {
+    device_state_free(D);
+    D = new DeviceState();
+    P->dev = D;
+    D->device = dev;
+    // gate factors stay complex128 in every precision form
+    const std::vector<double> host = leaf_host(P, D->leaf_elem_off);
+    double *lb = nullptr;
+    if (int rc = upload(&lb, host, "hipMalloc(leaves)")) return rc;
+    D->leafbuf = lb;
+    // pinned host memory the slice sum writes the final partials to
+    HIP_TRY(hipHostMalloc((void **)&D->host_partials, std::max<uint64_t>(P->net.B, 1) * sizeof(qtn_partial),
+                          hipHostMallocMapped));
+    HIP_TRY(hipHostGetDevicePointer((void **)&D->host_partials_dev, D->host_partials, 0));
+  }
+  if (int rc = set_program_lds(lds_total)) return rc;
+  LaunchGraph lg;
+  try {
+    static const int env_streams = [] {
+      const char *e = std::getenv("QTN_STREAMS");  // tuning switch: 1 serialises every launch
+      return e ? std::max(1, std::min(1 + DeviceState::kSide, std::atoi(e))) : 1 + DeviceState::kSide;
+    }();
+    lg = launch_graph(sch, X, L, P->net.B, L.S, P->precision != QTN_FP64, env_streams);
+  } catch (const std::exception &e) {
+    set_error(e.what());
+    return QTN_ESTATE;
+  }
+  for (int k = 0; k + 1 < lg.nstreams; ++k) {
+    if (!D->side[k]) HIP_TRY(hipStreamCreateWithFlags(&D->side[k], hipStreamNonBlocking));
+    if (!D->join_ev[k]) HIP_TRY(hipEventCreateWithFlags(&D->join_ev[k], hipEventDisableTiming));
+  }
+  if (!D->fork_ev) HIP_TRY(hipEventCreateWithFlags(&D->fork_ev, hipEventDisableTiming));
+  while (D->unit_ev.size() < lg.deps.size()) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    D->unit_ev.push_back(e);
+  }
+  drop_graph(D);
+  D->lg = lg;
+  D->mode = mode;
+  D->ws = (char *)dev_ptr;
+  D->ws_bytes = bytes;
+  // the exponent words start cleared; the slice sum clears them after each wave
+  if (P->precision != QTN_FP64 && L.exp_bytes) HIP_TRY(hipMemset(D->ws + L.data_bytes, 0, L.exp_bytes));
+  D->L = L;
+  D->max_slots = max_slots;
+  D->lds_bytes = lds_bytes;
+  D->lds_total = lds_total;
+  D->desc_bytes = desc_off;
+  std::vector<char> blob;
+  fill_tables(P, D, X, blob);
   if (blob.size() > 0xffffffffull) {
     set_error("program descriptors too large");
     return QTN_ESTATE;
@@ -1522,17 +1889,17 @@ static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint
   switch (d.nf32) {
 #define QTN_NF(F)                                                                                  \
   case F:                                                                                          \
-    if constexpr (F <= NV)                                                                         \
+    if constexpr (F <= NV && (SCALE || F == 0)) /* FP64 plans store nothing in 8 bytes */        \
     {                                                                                              \
       if (d.tiled_lds && d.tiled_fold == 0)                                                        \
         hipLaunchKernelGGL((step_tiled<SCALE, NK, NV, (F <= NV ? F : 0), true>), grid, dim3(256),  \
-                           d.tiled_lds, stream, d, nb, ns, s_lo, jspan);                           \
+                           d.tiled_lds + d.dot_lds, stream, d, nb, ns, s_lo, jspan);               \
       else if (d.tiled_lds)                                                                        \
         hipLaunchKernelGGL((step_tiled<SCALE, NK, NV, (F <= NV ? F : 0), false>), grid, dim3(256), \
-                           d.tiled_lds, stream, d, nb, ns, s_lo, jspan);                           \
+                           d.tiled_lds + d.dot_lds, stream, d, nb, ns, s_lo, jspan);               \
       else                                                                                         \
-        hipLaunchKernelGGL((step_stream<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256), 0,    \
-                           stream, d, nb, ns, s_lo, jspan);                                        \
+        hipLaunchKernelGGL((step_stream<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256),       \
+                           d.dot_lds, stream, d, nb, ns, s_lo, jspan);                             \
     }                                                                                              \
     break;
     QTN_NF(0) QTN_NF(1) QTN_NF(2) QTN_NF(3) QTN_NF(4)
@@ -1564,15 +1931,62 @@ static void launch_stream(const PStep &d, dim3 grid, hipStream_t stream, uint32_
   }
 }
 
+// Launches grid-wide step `st` for the wave of `cnt` slices starting at
+// s_lo.  Streaming steps: units of jspan x 256 elements, about tu.target
+// blocks over the chip, each walking up to 32 rows, so that the per-block
+// set-up (index tables, instance offsets and kappa coefficients, a chain of
+// dependent loads) is paid once per up to 8192 outputs; the default of 1024
+// (4 per compute unit) was measured best on the n=120 steps (2048 to 8192 up
+// to 3x slower for the direct kernels, 256 slower, 512 about even), and
+// qtn_plan_autotune measures the alternatives per step.  A folding step
+// reports its grid.x (the partial slots the slice sum reads) in *dot_gx.
 template <bool SCALE>
-static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream, bool concurrent) {
-  DeviceState *D = P->dev;
+static int launch_grid_step(const qtn_plan_t *P, const DeviceState *D, int st, hipStream_t stream, uint64_t s_lo,
+                            uint64_t cnt, const StepTune &tu, uint32_t *dot_gx) {
+  const Schedule &sch = P->sched;
+  const uint64_t B = P->net.B;
+  PStep d = D->steps[st];
+  if (d.dot) d.dotp = D->blobbuf + D->dot_args_off;
+  if (tu.stream_only) d.tiled_lds = 0;
+  const uint32_t nb = sch.steps[st].bdep ? (uint32_t)B : 1;
+  const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
+  const uint64_t Q = (uint64_t)nb * ns;
+  const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
+  if (d.dot && !streaming) {
+    set_error("internal: the folded closing chain sits on a step that does not stream");
+    return QTN_ESTATE;
+  }
+  if (streaming) {
+    const uint64_t target = tu.target;
+    const uint32_t rows = (1u << d.rC) >> 8;
+    uint32_t jspan = 32;
+    while (jspan > 1 && (uint64_t)(rows / jspan) * Q < target) jspan >>= 1;
+    const uint64_t units = rows / jspan;
+    const uint64_t want = std::max<uint64_t>(1, 2 * target / std::max<uint64_t>(Q, 1));
+    const dim3 grid((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
+    if (d.dot && dot_gx) *dot_gx = grid.x;
+    launch_stream<SCALE>(d, grid, stream, nb, ns, s_lo, jspan);
+  } else {
+    const uint64_t total = Q << d.rC;
+    const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
+    hipLaunchKernelGGL((step_small<SCALE>), dim3(blocks), dim3(256), 0, stream, d, nb, ns, s_lo);
+  }
+  return QTN_OK;
+}
+
+template <bool SCALE>
+static int run_waves(qtn_plan_t *P, DeviceState *D, uint64_t lo, uint64_t hi, hipStream_t stream,
+                     bool concurrent) {
   const Schedule &sch = P->sched;
   const ExecPlan &X = P->exec[D->mode];
   const uint64_t S = D->L.S;
   const uint64_t B = P->net.B;
   qtn_partial *partials = (qtn_partial *)(D->ws + D->L.partial_off);
-  const Tensor &res = sch.tensors[sch.result];
+  // the slice sum reads the result tensor, or with a folded closing chain the
+  // block partials and exponents of the folding step's output
+  const bool folded = X.dot_step >= 0;
+  const Tensor &res = sch.tensors[folded ? X.dot_tensor : sch.result];
+  uint32_t dot_gx = 0;
   const uint64_t scratch_stride = (X.scratch_per_wg + 255) & ~uint64_t(255);
   bool first = true;
   const LaunchGraph &lg = D->lg;
@@ -1611,12 +2025,26 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
                              s_lo + S >= hi ? D->host_partials_dev : (qtn_partial *)nullptr,
                              (SCALE && D->L.exp_bytes) ? (uint32_t *)(D->ws + D->L.data_bytes) : (uint32_t *)nullptr,
                              D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
-                             SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0);
+                             SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0,
+                             folded ? (const double2 *)(D->ws + D->L.dot_off) : (const double2 *)nullptr,
+                             (uint64_t)D->L.dot_slots, dot_gx);
           first = false;
         } else {
           const size_t g = (size_t)(u - 1);
           const LaunchGroup &G = X.launches[g];
           if (G.kind == 0) {
+            const bool timed = D->timing;
+            double tb = 0, tf = 0;
+            if (timed) {
+              if (D->ev_used + 2 > D->ev.size()) {
+                for (int j = 0; j < 64; ++j) {
+                  hipEvent_t e;
+                  HIP_TRY(hipEventCreate(&e));
+                  D->ev.push_back(e);
+                }
+              }
+              HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
+            }
             // at most kMaxGroupProgs programs per launch
             for (size_t p0 = 0; p0 < G.programs.size(); p0 += kMaxGroupProgs) {
               GroupArgs ga;
@@ -1625,28 +2053,40 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
               for (size_t k = p0; k < G.programs.size() && k < p0 + kMaxGroupProgs; ++k) {
                 const Program &pr = X.programs[G.programs[k]];
                 const uint32_t j = ga.nprog++;
-                total += (pr.bdep ? B : 1) * (pr.sdep ? cnt : 1);
-                ga.blob_off[j] = (uint32_t)D->blob_off[G.programs[k]];
+                const uint64_t items = (pr.bdep ? B : 1) * (pr.sdep ? cnt : 1);
+                total += items;
+                tb += (double)items * D->prog_bytes[G.programs[k]];
+                tf += (double)items * D->prog_flops[G.programs[k]];
                 ga.item_end[j] = (uint32_t)total;
                 ga.nsteps[j] = (uint16_t)pr.steps.size();
                 ga.nstage[j] = (uint16_t)(pr.staged.size() + pr.staged_global.size());
                 ga.bdep[j] = pr.bdep ? 1 : 0;
                 ga.sdep[j] = pr.sdep ? 1 : 0;
+                ga.ns[j] = (uint32_t)cnt;
+                ga.blob[j] = D->blobbuf + D->blob_off[G.programs[k]];
+                ga.scratch[j] = D->ws + D->L.scratch_off;
+                ga.scratch_stride[j] = scratch_stride;
+                ga.s_lo[j] = s_lo;
               }
               const uint64_t cap = D->mode == MODE_SLICE ? D->L.wg_slots : 2048;
               const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
               hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), D->lds_total,
-                                 stream, (const char *)D->blobbuf, ga, (uint32_t)B, (uint32_t)total, s_lo,
-                                 (uint32_t)cnt, D->ws + D->L.scratch_off, scratch_stride,
-                                 D->lds_bytes, D->max_slots, D->desc_bytes);
+                                 stream, ga, (uint32_t)total, D->lds_bytes, D->max_slots, D->desc_bytes);
+            }
+            if (timed) {
+              HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
+              D->ev_used += 2;
+              D->ev_bytes.push_back(tb);
+              D->ev_flops.push_back(tf);
+              D->ev_step.push_back(-1);
             }
           } else {
             const int st = G.step;
-            const PStep &d = D->steps[st];
             const uint32_t nb = sch.steps[st].bdep ? (uint32_t)B : 1;
             const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
             const uint64_t Q = (uint64_t)nb * ns;
-            const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
+            const PStep &d0 = D->steps[st];
+            const bool streaming = d0.rC >= kStreamMinRank && d0.nk <= 4 && d0.nvary >= 1 && d0.nvary <= 4;
             const bool timed = D->timing && streaming;
             if (timed) {
               if (D->ev_used + 2 > D->ev.size()) {
@@ -1658,28 +2098,8 @@ static int run_waves(qtn_plan_t *P, uint64_t lo, uint64_t hi, hipStream_t stream
               }
               HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
             }
-            if (streaming) {
-              // units of jspan x 256 elements: about 1024 blocks over the chip
-              // (4 per compute unit), each walking up to 32 rows, so that the
-              // per-block set-up (index tables, instance offsets and kappa
-              // coefficients, a chain of dependent loads) is paid once per up
-              // to 8192 outputs.  Measured on the n=120 steps: 2048 to 8192
-              // blocks are slower for both kernels (up to 3x for the direct
-              // ones), 256 is slower, 512 is about even.
-              const uint64_t target = 1024;
-              const uint32_t rows = (1u << d.rC) >> 8;
-              uint32_t jspan = 32;
-              while (jspan > 1 && (uint64_t)(rows / jspan) * Q < target) jspan >>= 1;
-              const uint64_t units = rows / jspan;
-              const uint64_t want = std::max<uint64_t>(1, 2 * target / std::max<uint64_t>(Q, 1));
-              const dim3 grid((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
-              launch_stream<SCALE>(d, grid, stream, nb, ns, s_lo, jspan);
-            } else {
-              const uint64_t total = Q << d.rC;
-              const unsigned blocks =
-                  (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((total + 255) / 256, 16384));
-              hipLaunchKernelGGL((step_small<SCALE>), dim3(blocks), dim3(256), 0, stream, d, nb, ns, s_lo);
-            }
+            const StepTune tu = D->tune.empty() ? StepTune() : D->tune[st];
+            if (int rc = launch_grid_step<SCALE>(P, D, st, stream, s_lo, cnt, tu, &dot_gx)) return rc;
             if (timed) {
               HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
               D->ev_used += 2;
@@ -1751,8 +2171,8 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
     }
   }
   auto enqueue = [&](hipStream_t st, bool concurrent) {
-    return P->precision == QTN_FP64 ? run_waves<false>(P, lo, hi, st, concurrent)
-                                    : run_waves<true>(P, lo, hi, st, concurrent);
+    return P->precision == QTN_FP64 ? run_waves<false>(P, D, lo, hi, st, concurrent)
+                                    : run_waves<true>(P, D, lo, hi, st, concurrent);
   };
   if (D->use_graphs) {
     // The launch sequence of [lo, hi) is captured once on an internal stream
@@ -1823,10 +2243,18 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
         D->t_last_error = (int)te;
         continue;  // a sample that cannot be read is dropped, not an error
       }
+      const int st = D->ev_step[j / 2];
+      if (st < 0) {
+        // workgroup programs: counted apart from the streaming steps
+        D->t_prog.launches += 1;
+        D->t_prog.ms += ms;
+        D->t_prog.bytes += D->ev_bytes[j / 2];
+        D->t_prog.flops += D->ev_flops[j / 2];
+        continue;
+      }
       D->t_ms += ms;
       D->t_bytes += D->ev_bytes[j / 2];
       D->t_flops += D->ev_flops[j / 2];
-      const int st = D->ev_step[j / 2];
       if (st >= 0 && (size_t)st < D->t_step.size()) {
         D->t_step[st].launches += 1;
         D->t_step[st].ms += ms;
@@ -1853,6 +2281,287 @@ extern "C" int qtn_contract_async(qtn_plan_t *P, uint64_t lo, uint64_t hi, void 
   return contract_impl(P, lo, hi, stream, out, true);
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: launch configuration of each grid-wide streaming step, measured.
+// ---------------------------------------------------------------------------
+static uint64_t step_signature(const PStep &d, uint64_t Q) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (v >> (8 * i)) & 255u;
+      h *= 1099511628211ull;
+    }
+  };
+  mix((uint64_t)d.rC | (uint64_t)d.nk << 8 | (uint64_t)d.nvary << 16 | (uint64_t)d.nf32 << 24 |
+      (uint64_t)d.nin << 32 | (uint64_t)d.dot << 40 | (uint64_t)(d.tiled_fold + 1) << 48);
+  mix(d.tiled_lds);
+  mix(Q);
+  for (int i = 0; i < d.nin; ++i) mix((uint64_t)d.in[i].mask | (uint64_t)d.in[i].f64 << 32 | (uint64_t)d.in[i].loc << 40);
+  return h;
+}
+
+template <bool SCALE>
+static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_path, qtn_tune_stats *st) {
+  DeviceState *D = P->dev;
+  const Schedule &sch = P->sched;
+  const ExecPlan &X = P->exec[D->mode];
+  const uint64_t nsl = 1ull << P->cut.size();
+  const uint64_t cnt = std::min<uint64_t>(D->L.S, nsl);
+  // cache: one line per signature, "<hex signature> <target> <stream_only> <us>"
+  std::map<uint64_t, StepTune> cache;
+  if (cache_path && cache_path[0])
+    if (FILE *f = std::fopen(cache_path, "r")) {
+      unsigned long long sig;
+      unsigned target;
+      int so;
+      double us;
+      while (std::fscanf(f, "%llx %u %d %lf", &sig, &target, &so, &us) == 4) {
+        StepTune t;
+        t.target = target;
+        t.stream_only = so != 0;
+        cache[(uint64_t)sig] = t;
+      }
+      std::fclose(f);
+    }
+  D->tune.assign(sch.steps.size(), StepTune());
+  drop_graph(D);
+  // the inputs of every step exist after one contraction of the first wave
+  if (int rc = run_waves<SCALE>(P, D, 0, cnt, stream, false)) return rc;
+  if (int rc = wait_stream(stream, "qtn_plan_autotune")) return rc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  std::vector<std::pair<uint64_t, std::pair<StepTune, double>>> learned;
+  int rc = QTN_OK;
+  for (const LaunchGroup &G : X.launches) {
+    if (G.kind != 1) continue;
+    const int s_ = G.step;
+    const PStep &d = D->steps[s_];
+    const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
+    if (!streaming) continue;
+    const uint64_t Q = (uint64_t)(sch.steps[s_].bdep ? P->net.B : 1) * (sch.steps[s_].sdep ? cnt : 1);
+    const uint64_t sig = step_signature(d, Q);
+    ++st->steps;
+    auto hit = cache.find(sig);
+    if (hit != cache.end()) {
+      D->tune[s_] = hit->second;
+      ++st->cached;
+      continue;
+    }
+    // (timing of garbage inputs: every launch reads only its own operands'
+    // memory, which later tensors may have reused; the timing is unchanged and
+    // the state is rebuilt by the next contraction)
+    double best_us = 0, default_us = 0;
+    StepTune best;
+    for (uint32_t target : {256u, 512u, 1024u, 2048u})
+      for (int so = 0; so < (d.tiled_lds ? 2 : 1); ++so) {
+        StepTune t;
+        t.target = target;
+        t.stream_only = so != 0;
+        uint32_t gx = 0;
+        if ((rc = launch_grid_step<SCALE>(P, D, s_, stream, 0, cnt, t, &gx))) break;
+        constexpr int R = 5;
+        if (hipEventRecord(e0, stream) != hipSuccess) break;
+        for (int r = 0; r < R && !rc; ++r) rc = launch_grid_step<SCALE>(P, D, s_, stream, 0, cnt, t, &gx);
+        if (rc || hipEventRecord(e1, stream) != hipSuccess) break;
+        if ((rc = wait_stream(stream, "qtn_plan_autotune"))) break;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = hip_fail(hipGetLastError(), "hipEventElapsedTime");
+          break;
+        }
+        const double us = 1e3 * ms / R;
+        ++st->measured;
+        if (target == 1024 && so == 0) default_us = us;
+        if (best_us == 0 || us < best_us) {
+          best_us = us;
+          best = t;
+        }
+      }
+    if (rc) break;
+    D->tune[s_] = best;
+    st->default_us += default_us;
+    st->tuned_us += best_us;
+    learned.push_back({sig, {best, best_us}});
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  // the measurements raised exponent words: start the next contraction clean
+  if (SCALE && D->L.exp_bytes) HIP_TRY(hipMemsetAsync(D->ws + D->L.data_bytes, 0, D->L.exp_bytes, stream));
+  if (int w = wait_stream(stream, "qtn_plan_autotune")) return w;
+  if (cache_path && cache_path[0] && !learned.empty()) {
+    FILE *f = std::fopen(cache_path, "a");
+    if (!f) {
+      set_error(std::string("cannot append to autotune cache ") + cache_path);
+      return QTN_EINVAL;
+    }
+    for (const auto &l : learned)
+      std::fprintf(f, "%016llx %u %d %.3f\n", (unsigned long long)l.first, l.second.first.target,
+                   l.second.first.stream_only ? 1 : 0, l.second.second);
+    std::fclose(f);
+  }
+  return QTN_OK;
+}
+
+extern "C" int qtn_plan_autotune(qtn_plan_t *P, void *stream_v, const char *cache_path, qtn_tune_stats *stats) {
+  set_error("");
+  if (!P || !stats) {
+    set_error("NULL argument");
+    return QTN_EINVAL;
+  }
+  if (!P->dev || !P->dev->ws) {
+    set_error("no workspace bound");
+    return QTN_ENOMEM;
+  }
+  if (P->dev->timing) {
+    set_error("turn timing off before tuning");
+    return QTN_ESTATE;
+  }
+  std::memset(stats, 0, sizeof(*stats));
+  const hipStream_t stream = (hipStream_t)stream_v;
+  return P->precision == QTN_FP64 ? autotune_impl<false>(P, stream, cache_path, stats)
+                                  : autotune_impl<true>(P, stream, cache_path, stats);
+}
+
+// ---------------------------------------------------------------------------
+// Several circuits in one persistent launch: the whole-schedule programs of
+// plans bound in one-workgroup-per-instance mode share one wg_programs
+// launch, whose workgroups take (plan, bitstring, slice) items from all of
+// them; each plan's slice sum follows.
+// ---------------------------------------------------------------------------
+template <bool SCALE>
+static int batch_enqueue(qtn_plan_t *const *plans, uint32_t n, const uint64_t *lo, const uint64_t *hi,
+                         hipStream_t stream) {
+  GroupArgs ga;
+  std::memset(&ga, 0, sizeof(ga));
+  uint64_t total = 0, cap = ~0ull;
+  uint32_t lds_bytes = 0, desc_bytes = 0;
+  int max_slots = 1;
+  for (uint32_t i = 0; i < n; ++i) {
+    qtn_plan_t *P = plans[i];
+    DeviceState *D = P->dev;
+    if (lo[i] == hi[i]) continue;
+    const Program &pr = P->exec[MODE_SLICE].programs[0];
+    const uint64_t cnt = hi[i] - lo[i];
+    const uint32_t j = ga.nprog++;
+    total += (pr.bdep ? P->net.B : 1) * (pr.sdep ? cnt : 1);
+    ga.item_end[j] = (uint32_t)total;
+    ga.nsteps[j] = (uint16_t)pr.steps.size();
+    ga.nstage[j] = (uint16_t)(pr.staged.size() + pr.staged_global.size());
+    ga.bdep[j] = pr.bdep ? 1 : 0;
+    ga.sdep[j] = pr.sdep ? 1 : 0;
+    ga.ns[j] = (uint32_t)cnt;
+    ga.blob[j] = D->blobbuf + D->blob_off[0];
+    ga.scratch[j] = D->ws + D->L.scratch_off;
+    ga.scratch_stride[j] = (P->exec[MODE_SLICE].scratch_per_wg + 255) & ~uint64_t(255);
+    ga.s_lo[j] = lo[i];
+    cap = std::min<uint64_t>(cap, std::max<uint64_t>(1, D->L.wg_slots));
+    lds_bytes = std::max(lds_bytes, D->lds_bytes);
+    max_slots = std::max(max_slots, D->max_slots);
+    desc_bytes = std::max(desc_bytes, D->lds_total - D->desc_bytes);
+  }
+  if (ga.nprog) {
+    // one LDS layout that holds every program: the largest tensor region,
+    // slot count and descriptor region
+    const uint32_t desc_off = (lds_bytes + 256 * 16 + (uint32_t)(2 * max_slots + 4) * 4 + 15) & ~15u;
+    const uint32_t lds_total = desc_off + desc_bytes;
+    if (lds_total > 160 * 1024) {
+      set_error("the programs of the batch do not fit one LDS layout");
+      return QTN_ESTATE;
+    }
+    if (int rc = set_program_lds(lds_total)) return rc;
+    const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
+    hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), lds_total, stream, ga,
+                       (uint32_t)total, lds_bytes, max_slots, desc_off);
+  }
+  for (uint32_t i = 0; i < n; ++i) {
+    qtn_plan_t *P = plans[i];
+    if (lo[i] == hi[i]) continue;
+    DeviceState *D = P->dev;
+    const Schedule &sch = P->sched;
+    const Tensor &res = sch.tensors[sch.result];
+    const uint64_t S = D->L.S, B = P->net.B;
+    const uint64_t rb = res.bdep ? (res.sdep ? S : 1) : 0, rs = res.sdep ? 1 : 0;
+    hipLaunchKernelGGL((slice_sum<SCALE>), dim3((unsigned)B), dim3(256), 0, stream,
+                       (const void *)(D->ws + res.data_off), res.f64 ? 1u : 0u,
+                       (const int *)(D->ws + res.exp_off), rb, rs, (uint32_t)(hi[i] - lo[i]),
+                       P->net.prefactor, (qtn_partial *)(D->ws + D->L.partial_off), 1,
+                       D->host_partials_dev,
+                       (SCALE && D->L.exp_bytes) ? (uint32_t *)(D->ws + D->L.data_bytes) : (uint32_t *)nullptr,
+                       D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
+                       SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0,
+                       (const double2 *)nullptr, (uint64_t)0, 0u);
+  }
+  HIP_TRY(hipGetLastError());
+  return QTN_OK;
+}
+
+extern "C" int qtn_batch_contract(qtn_plan_t *const *plans, uint32_t n_plans, const uint64_t *slice_lo,
+                                  const uint64_t *slice_hi, void *stream_v, qtn_partial *out) {
+  set_error("");
+  if (!plans || !slice_lo || !slice_hi || !out || n_plans == 0) {
+    set_error("NULL argument or no plans");
+    return QTN_EINVAL;
+  }
+  if (n_plans > (uint32_t)kMaxGroupProgs) {
+    set_error("at most " + std::to_string(kMaxGroupProgs) + " plans per batch");
+    return QTN_EINVAL;
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  const int prec = plans[0] ? plans[0]->precision : 0;
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < n_plans; ++i) {
+    qtn_plan_t *P = plans[i];
+    if (!P || !P->dev || !P->dev->ws) {
+      set_error("plan " + std::to_string(i) + " has no bound workspace");
+      return QTN_ENOMEM;
+    }
+    if (P->dev->device != dev) {
+      set_error("plan " + std::to_string(i) + " is bound on another device");
+      return QTN_ESTATE;
+    }
+    if (P->dev->mode != MODE_SLICE) {
+      set_error("plan " + std::to_string(i) + " is not bound in one-workgroup-per-instance mode (exec_mode 1)");
+      return QTN_ESTATE;
+    }
+    if ((P->precision == QTN_FP64) != (prec == QTN_FP64)) {
+      set_error("the plans of a batch share one precision form");
+      return QTN_EINVAL;
+    }
+    const uint64_t nsl = 1ull << P->cut.size();
+    if (slice_lo[i] > slice_hi[i] || slice_hi[i] > nsl) {
+      set_error("plan " + std::to_string(i) + ": slice range outside [0, 2^k)");
+      return QTN_ERANGE;
+    }
+    if (slice_hi[i] - slice_lo[i] > P->dev->L.S) {
+      set_error("plan " + std::to_string(i) + ": the range exceeds its slices per wave (one wave per plan)");
+      return QTN_ERANGE;
+    }
+    for (uint32_t j = 0; j < i; ++j)
+      if (plans[j] == P) {
+        set_error("a plan appears twice in the batch (its workspace would be shared)");
+        return QTN_EINVAL;
+      }
+    total += P->net.B;
+  }
+  hipStream_t stream = (hipStream_t)stream_v;
+  const int rc = prec == QTN_FP64 ? batch_enqueue<false>(plans, n_plans, slice_lo, slice_hi, stream)
+                                  : batch_enqueue<true>(plans, n_plans, slice_lo, slice_hi, stream);
+  if (rc) return rc;
+  if (int w = wait_stream(stream, "qtn_batch_contract")) return w;
+  uint64_t at = 0;
+  for (uint32_t i = 0; i < n_plans; ++i) {
+    qtn_plan_t *P = plans[i];
+    for (uint64_t b = 0; b < P->net.B; ++b)
+      out[at + b] = slice_lo[i] == slice_hi[i] ? qtn_partial{0.0, 0.0, 0.0, 0.0} : P->dev->host_partials[b];
+    at += P->net.B;
+  }
+  (void)total;
+  return QTN_OK;
+}
+
 extern "C" int qtn_plan_set_graphs(qtn_plan_t *P, int enable) {
   if (!P || !P->dev) {
     set_error("bind a workspace first");
@@ -1874,6 +2583,7 @@ extern "C" int qtn_plan_set_timing(qtn_plan_t *P, int enable) {
   D->t_launches = D->t_failed = 0;
   D->t_last_error = 0;
   D->t_step.assign(P->sched.steps.size(), DeviceState::StepTiming());
+  D->t_prog = DeviceState::StepTiming();
   return QTN_OK;
 }
 
@@ -1897,13 +2607,18 @@ extern "C" int qtn_plan_step_timing(const qtn_plan_t *P, int32_t step, qtn_kerne
     set_error("bind a workspace first");
     return QTN_ESTATE;
   }
-  if (step < 0 || (size_t)step >= P->sched.steps.size()) {
+  if (step < -1 || step >= (int32_t)P->sched.steps.size()) {
     set_error("step out of range");
     return QTN_ERANGE;
   }
   const DeviceState *D = P->dev;
   std::memset(out, 0, sizeof(*out));
-  if ((size_t)step < D->t_step.size()) {
+  if (step == -1) {
+    out->launches = D->t_prog.launches;
+    out->total_ms = D->t_prog.ms;
+    out->alg_bytes = D->t_prog.bytes;
+    out->alg_flops = D->t_prog.flops;
+  } else if ((size_t)step < D->t_step.size()) {
     const DeviceState::StepTiming &T = D->t_step[step];
     out->launches = T.launches;
     out->total_ms = T.ms;
@@ -1937,7 +2652,8 @@ extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *nam
         k = std::string(d.tiled_lds ? "step_tiled<" : "step_stream<") + tf + ", " +
             std::to_string(d.nk) + ", " + std::to_string(d.nvary) + ", " +
             std::to_string(d.nf32 <= d.nvary ? d.nf32 : 0) +
-            (d.tiled_lds ? (d.tiled_fold == 0 ? ", true>" : ", false>") : ">");
+            (d.tiled_lds ? (d.tiled_fold == 0 ? ", true>" : ", false>") : ">") +
+            (d.dot ? " + closing-chain reduction" : "");
     }
   std::strncpy(name, k.c_str(), capacity - 1);
   name[capacity - 1] = 0;

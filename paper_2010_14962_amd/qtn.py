@@ -33,7 +33,9 @@ class QtnPlanOpts(ctypes.Structure):
     _fields_ = [("k", c_int32), ("max_rank", c_int32), ("k_max", c_int32),
                 ("cut_vars", POINTER(c_uint32)), ("seed", c_uint64),
                 ("ga_pop", c_int32), ("ga_iters", c_int32), ("precision", c_int32),
-                ("fuse_chains", c_int32), ("exec_mode", c_int32)]
+                ("fuse_chains", c_int32), ("exec_mode", c_int32),
+                ("use_cost_model", c_int32), ("offspring_factor", c_int32),
+                ("cost_model", c_void_p), ("density_matrix", c_int32)]
 
 
 class QtnPartial(ctypes.Structure):
@@ -51,7 +53,7 @@ class QtnPlanInfo(ctypes.Structure):
                 ("search_seconds", c_double), ("precision", c_int32),
                 ("f64_below_rank", c_int32), ("n_programs_wide", c_int32),
                 ("n_launches_wide", c_int32), ("slice_lds_bytes", c_uint32),
-                ("slice_scratch_bytes", c_double)]
+                ("slice_scratch_bytes", c_double), ("mf_width", c_int32)]
 
 
 class QtnKernelTiming(ctypes.Structure):
@@ -62,6 +64,16 @@ class QtnKernelTiming(ctypes.Structure):
 class QtnSearchStats(ctypes.Structure):
     _fields_ = [("seconds", c_double), ("exact_evals", c_uint64), ("model_evals", c_uint64),
                 ("width", c_int32), ("log2_cost", c_double)]
+
+
+class QtnRangeStats(ctypes.Structure):
+    _fields_ = [("ranges", c_uint64), ("contracted", c_uint64), ("resumed", c_uint64),
+                ("retried", c_uint64)]
+
+
+class QtnTuneStats(ctypes.Structure):
+    _fields_ = [("steps", c_uint32), ("measured", c_uint32), ("cached", c_uint32),
+                ("default_us", c_double), ("tuned_us", c_double)]
 
 
 class QtnError(RuntimeError):
@@ -80,7 +92,9 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_cost_features", "qtn_cost_exact", "qtn_mlp_create", "qtn_mlp_destroy",
            "qtn_mlp_num_params", "qtn_mlp_get_params", "qtn_mlp_set_params", "qtn_mlp_get_grads",
            "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search",
-           "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_contract_async"]
+           "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_contract_async",
+           "qtn_contract_ranges", "qtn_plan_fingerprint", "qtn_plan_inject_faults",
+           "qtn_batch_contract", "qtn_plan_autotune"]
 COST_FEATURES = 32
 
 
@@ -140,6 +154,13 @@ def lib():
                                      c_void_p, pf]
     L.qtn_cut_search.argtypes = [POINTER(QtnGraph), c_uint32, c_uint32, c_int32, c_int32,
                                  c_uint64, c_void_p, c_int32, pu32, POINTER(QtnSearchStats)]
+    L.qtn_contract_ranges.argtypes = [c_void_p, c_uint64, c_int32, c_char_p, c_void_p,
+                                      POINTER(QtnPartial), POINTER(QtnRangeStats)]
+    L.qtn_plan_fingerprint.argtypes = [c_void_p, POINTER(c_uint64)]
+    L.qtn_plan_autotune.argtypes = [c_void_p, c_void_p, c_char_p, POINTER(QtnTuneStats)]
+    L.qtn_batch_contract.argtypes = [POINTER(c_void_p), c_uint32, POINTER(c_uint64), POINTER(c_uint64),
+                                     c_void_p, POINTER(QtnPartial)]
+    L.qtn_plan_inject_faults.argtypes = [c_void_p, c_uint64, c_int32]
     for name in EXPORTS:
         if name not in ("qtn_plan_opts_default", "qtn_plan_destroy", "qtn_last_error",
                         "qtn_mlp_destroy"):
@@ -279,13 +300,37 @@ class Plan:
         _check(lib().qtn_contract(self._h, slice_lo, slice_hi, c_void_p(stream or 0), out))
         return [out[i] for i in range(self.n_bitstrings)]
 
+    def contract_ranges(self, range_slices: int, max_retries: int = 0,
+                        checkpoint: Optional[str] = None, stream: Optional[int] = None):
+        """All slices as ranges of range_slices, re-issuing failed ranges and
+        keeping a JSONL checkpoint; returns (partials, stats dict)."""
+        out = (QtnPartial * self.n_bitstrings)()
+        st = QtnRangeStats()
+        _check(lib().qtn_contract_ranges(self._h, range_slices, max_retries,
+                                         checkpoint.encode() if checkpoint else None,
+                                         c_void_p(stream or 0), out, byref(st)))
+        return [out[i] for i in range(self.n_bitstrings)], {
+            "ranges": st.ranges, "contracted": st.contracted, "resumed": st.resumed,
+            "retried": st.retried}
+
+    def fingerprint(self) -> int:
+        v = c_uint64()
+        _check(lib().qtn_plan_fingerprint(self._h, byref(v)))
+        return v.value
+
+    def inject_faults(self, slice_lo: int, count: int) -> None:
+        _check(lib().qtn_plan_inject_faults(self._h, slice_lo, count))
+
 
 def qtn_plan(n: int, edges: Sequence, p: int, gamma: Sequence[float], beta: Sequence[float],
              bitstrings, k: int = -1, max_rank: int = 0, k_max: int = 24,
              cut_vars: Optional[Sequence[int]] = None, seed: int = 0, ga_pop: int = 11,
              ga_iters: int = 4, precision: str = "fp64", fuse_chains: bool = True,
-             exec_mode: str = "auto") -> Plan:
-    """Builds a plan (host only): network, cut set, order and schedule."""
+             exec_mode: str = "auto", cost_model=None, offspring_factor: int = 16,
+             use_cost_model: Optional[bool] = None, density_matrix: bool = False) -> Plan:
+    """Builds a plan: network, cut set, order and schedule (host only, except
+    that a cost model ranks search candidates on its device).  With
+    `cost_model` (a CostMLP) the cut search is the model-guided one."""
     L = lib()
     e = _u32(edges).reshape(-1)
     g = QtnGraph(n, len(e) // 2, e.ctypes.data_as(POINTER(c_uint32)))
@@ -303,6 +348,12 @@ def qtn_plan(n: int, edges: Sequence, p: int, gamma: Sequence[float], beta: Sequ
     opts.precision = PRECISIONS[precision]
     opts.fuse_chains = 1 if fuse_chains else 0
     opts.exec_mode = {"auto": -1, "wide": 0, "slice": 1}[exec_mode]
+    if use_cost_model is None:
+        use_cost_model = cost_model is not None
+    opts.use_cost_model = 1 if use_cost_model else 0
+    opts.offspring_factor = offspring_factor
+    opts.cost_model = cost_model.handle.value if cost_model is not None else None
+    opts.density_matrix = 1 if density_matrix else 0
     cv = None
     if cut_vars is not None:
         cv = _u32(cut_vars)
@@ -319,6 +370,22 @@ def qtn_partial_combine(a: QtnPartial, b: QtnPartial) -> QtnPartial:
     out = QtnPartial()
     _check(lib().qtn_partial_combine(byref(a), byref(b), byref(out)))
     return out
+
+
+def batch_contract(plans: Sequence["Plan"], ranges: Sequence[tuple], stream: Optional[int] = None):
+    """Several plans (bound with exec_mode="slice", one wave each) in one
+    persistent launch; returns one list of partials per plan."""
+    n = len(plans)
+    hs = (c_void_p * n)(*[p._h.value for p in plans])
+    lo = (c_uint64 * n)(*[int(r[0]) for r in ranges])
+    hi = (c_uint64 * n)(*[int(r[1]) for r in ranges])
+    out = (QtnPartial * sum(p.n_bitstrings for p in plans))()
+    _check(lib().qtn_batch_contract(hs, n, lo, hi, c_void_p(stream or 0), out))
+    res, at = [], 0
+    for p in plans:
+        res.append([out[at + i] for i in range(p.n_bitstrings)])
+        at += p.n_bitstrings
+    return res
 
 
 def plan_instance(inst, **kw) -> Plan:

@@ -1,0 +1,37 @@
+"""The autotuner of the launch configuration (qtn_plan_autotune): it times
+the alternatives of every streaming step, keeps the fastest, reuses a cache of
+earlier choices, and leaves the amplitudes unchanged (the block partition of
+a step changes, the arithmetic of its outputs does not)."""
+import pytest
+
+from instances import workload_instance
+from paper_2010_14962_amd import plan_instance
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autotune_keeps_results_and_caches(precision, tmp_path):
+    print("case autotune", precision, flush=True)
+    stream = torch.cuda.current_stream().cuda_stream
+    inst = workload_instance("qaoa_n120_p1_b8", seed=0)
+    plan = plan_instance(inst, k=0, precision=precision)
+    plan.bind_torch(1)
+    before = [p.value() for p in plan.contract(0, 1, stream)]
+    cache = str(tmp_path / "tune.txt")
+    st = plan.autotune(cache, stream)
+    print("autotune", st, flush=True)
+    assert st["steps"] > 0 and st["measured"] >= st["steps"] and st["cached"] == 0
+    assert st["tuned_us"] <= st["default_us"]
+    after = [p.value() for p in plan.contract(0, 1, stream)]
+    for a, b in zip(after, before):
+        assert abs(a - b) <= 1e-12 * abs(b)
+    again = [p.value() for p in plan.contract(0, 1, stream)]
+    assert again == after
+    # a second plan of the same workload takes every choice from the cache
+    other = plan_instance(inst, k=0, precision=precision)
+    other.bind_torch(1)
+    st2 = other.autotune(cache, stream)
+    assert st2["measured"] == 0 and st2["cached"] == st["steps"]
+    assert [p.value() for p in other.contract(0, 1, stream)] == after

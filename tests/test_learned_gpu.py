@@ -8,7 +8,7 @@ torch = pytest.importorskip("torch")
 
 from instances import make_instance
 from oracle.mlp import MLP64
-from paper_2010_14962_amd import qtn
+from paper_2010_14962_amd import plan_instance, qtn
 from paper_2010_14962_amd import learned as LM
 
 pytestmark = pytest.mark.gpu
@@ -119,20 +119,53 @@ def test_training_lowers_loss_and_generalises(trained):
     assert ev["spearman_log2_cost_fixed_k"] > 0.0
 
 
-def test_guided_search_rescored_and_bounded(trained):
+def test_guided_search_beats_algorithm1(trained):
+    """On 12 held-out (graph, seed) pairs (graphs unseen in training, n in
+    {80, 120}, p in {1, 2}, k = 12) the model-guided search returns cut sets
+    with a lower mean exact width than Algorithm 1 with exact fitness, at
+    about the same number of exact evaluations; every reported cost is an
+    exact re-score."""
     model, _, _ = trained
     specs = []
-    for n, p in ((120, 1), (80, 2)):
+    for n, p in ((120, 1), (80, 2), (120, 2), (80, 1)):
         inst = make_instance(n, p, 1, 7000 + n + p)
         specs.append(LM.GraphSpec(n, p, inst.edges, -1))
     N, T, F = 11, 4, 16
     rows = LM.gain_comparison(model, specs, 12, seeds=[0, 1, 2], pop=N, iters=T, factor=F)
     for r in rows:
         print(r["n"], r["p"], r["seed"], {k: (r[k]["width"], round(r[k]["log2_cost"], 2),
-                                             r[k]["exact_evals"]) for k in ("alg1", "guided", "unscreened", "random")})
+                                             r[k]["exact_evals"]) for k in ("alg1", "guided", "unscreened", "random")},
+              flush=True)
         g = r["guided"]
-        # every returned cut was re-scored exactly inside gain_comparison
         assert g["model_evals"] == F * (N - 1) * (T + 1)
         assert g["exact_evals"] <= N * (T + 2)
-    mean = lambda key: np.mean([r[key]["log2_cost"] for r in rows])
-    assert mean("guided") <= mean("alg1") + 0.5
+    assert len(rows) >= 8
+    mean = lambda key, f: float(np.mean([r[key][f] for r in rows]))
+    summary = {key: (mean(key, "width"), mean(key, "log2_cost"), mean(key, "exact_evals"))
+               for key in ("alg1", "guided", "unscreened", "random")}
+    print("mean (width, log2 cost, exact evaluations)", summary, flush=True)
+    # equal budget: the guided search scores no more sets exactly than Algorithm 1
+    assert mean("guided", "exact_evals") <= 1.25 * mean("alg1", "exact_evals")
+    assert mean("guided", "width") < mean("alg1", "width")
+    assert mean("guided", "width") < mean("unscreened", "width")
+
+
+def test_plan_with_cost_model_rescored_exactly(trained):
+    """qtn_plan with use_cost_model runs the model-guided search and keeps a
+    cut set whose cost is the exact one: the same set as qtn_cut_search with
+    the model, the plan's width equal to the exact evaluator's, and the
+    min-k search with a model meets the rank cap."""
+    model, _, _ = trained
+    inst = make_instance(80, 2, 1, 7081)
+    k = 10
+    plan = plan_instance(inst, k=k, seed=3, cost_model=model, offspring_factor=16)
+    cut = plan.cut()
+    ref, st = qtn.cut_search(80, inst.edges, 2, k, seed=3, model=model, offspring_factor=16)
+    assert cut == sorted(ref)
+    w, c = qtn.cost_exact(80, inst.edges, 2, np.array([cut], dtype=np.uint32))
+    assert plan.info()["mf_width"] == int(w[0]) == st["width"]
+    assert st["model_evals"] > 0
+    capped = plan_instance(inst, k=-1, max_rank=20, seed=3, cost_model=model)
+    wc, _ = qtn.cost_exact(80, inst.edges, 2, np.array([capped.cut()], dtype=np.uint32))
+    assert capped.info()["mf_width"] == int(wc[0]) <= 20
+    assert capped.info()["width"] <= 20
