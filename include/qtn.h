@@ -416,6 +416,29 @@ int qtn_cut_search(const qtn_graph *graph, uint32_t p, uint32_t k, int32_t pop, 
 int qtn_batch_contract(qtn_plan_t *const *plans, uint32_t n_plans, const uint64_t *slice_lo,
                        const uint64_t *slice_hi, void *stream, qtn_partial *out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * qtn_contract_async, but the workspace, the gate factors and the program
+ * descriptors live in a file-scope device array of QTN_NOALLOC_BYTES per
+ * GPU that the library holds from load until the process ends, and the
+ * partials go to device memory.  No workspace binding is needed and the call
+ * allocates nothing: it uploads the plan's constants into that array from
+ * host copies kept with the plan (hipMemcpyAsync on `stream`, so the plan
+ * must outlive any graph that captures the call), clears the exponent words
+ * with a kernel, and enqueues the contraction of slices [slice_lo, slice_hi)
+ * with `slices_per_wave` slices per wave on `stream`, one launch after
+ * another.  out_dev: n_bitstrings qtn_partial in device memory, written by
+ * the last kernel; valid after the stream is synchronised.  QTN_ENOMEM (with
+ * the bytes needed) when the plan's constants and workspace exceed the
+ * array.  Every call on one GPU uses the same array: calls that overlap on
+ * one GPU (other streams, other threads) race and must be serialised by the
+ * caller.  Results equal qtn_contract's for the same slices per wave.
+ */
+#define QTN_NOALLOC_BYTES (64ull << 20)
+int qtn_contract_noalloc(qtn_plan_t *plan, uint64_t slice_lo, uint64_t slice_hi,
+                         uint64_t slices_per_wave, void *stream, qtn_partial *out_dev);
+
 /* ---------------------------------------------------------------------------
  * Range-partitioned contraction with recovery.  The slices are independent
  * and the master sums one value per slice (Sec. III A); missing slices are

@@ -249,6 +249,7 @@ extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
 extern "C" void qtn_plan_destroy(qtn_plan_t *plan) {
   if (!plan) return;
   device_state_free(plan->dev);
+  noalloc_state_free(plan->na);
   delete plan;
 }
 

@@ -8,6 +8,7 @@
 
 namespace qtn {
 struct DeviceState;  // defined by the HIP runtime
+struct NoAllocState; // tables of qtn_contract_noalloc, defined by the HIP runtime
 constexpr uint32_t kLdsBudget = 56 * 1024;   // LDS bytes for program tensors
 constexpr uint64_t kMaxWorkgroups = 1024;    // persistent workgroups of a program launch
 
@@ -17,6 +18,7 @@ constexpr uint64_t kMaxWorkgroups = 1024;    // persistent workgroups of a progr
 int choose_mode(const struct qtn_plan_s *P, uint64_t S);
 uint64_t wg_slots_for(const struct qtn_plan_s *P, int mode, uint64_t S);
 void device_state_free(DeviceState *d);
+void noalloc_state_free(NoAllocState *n);
 void set_error(const std::string &msg);
 }  // namespace qtn
 
@@ -34,6 +36,7 @@ struct qtn_plan_s {
   int exec_mode = -1;      // -1 chosen per binding, else qtn::ExecMode
   qtn::ExecPlan exec[2];   // MODE_WIDE, MODE_SLICE
   qtn::DeviceState *dev = nullptr;
+  qtn::NoAllocState *na = nullptr;
   // a fault forced from the host for tests of re-issue: the next fault_count
   // range calls of qtn_contract_ranges that start at fault_lo fail
   uint64_t fault_lo = 0;

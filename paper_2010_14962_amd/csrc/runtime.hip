@@ -2562,6 +2562,155 @@ extern "C" int qtn_batch_contract(qtn_plan_t *const *plans, uint32_t n_plans, co
   return QTN_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Contraction without any allocation: the workspace, the gate factors and the
+// program descriptors live in one file-scope device array.
+// ---------------------------------------------------------------------------
+constexpr uint64_t kNoAllocBytes = QTN_NOALLOC_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+// Device address of `scratch` on each device, taken once per device with
+// that device current.  In host code the array's name is not a device
+// address; only these pointers are ever handed to kernels or copies.
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_address(int dev, char **out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device ordinal out of range");
+    return QTN_ESTATE;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p || ((uintptr_t)p & 255u)) {
+      set_error("scratch array has no aligned device address");
+      return QTN_EHIP;
+    }
+    g_scratch_ptr[dev] = (char *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return QTN_OK;
+}
+
+__global__ __launch_bounds__(256) void zero_words(uint32_t *p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+namespace qtn {
+// Host tables of a plan laid out in the scratch of one device: built on the
+// first call for (device, slices per wave) and kept with the plan.
+struct NoAllocState {
+  int device = -1;
+  uint64_t S = 0;
+  char *base = nullptr;
+  DeviceState D;              // its device pointers point into the scratch
+  std::vector<double> leaves; // uploaded by every call (the scratch is shared)
+  std::vector<char> blob;
+  uint64_t leaf_off = 0, blob_off = 0, ws_off = 0, total = 0;
+};
+
+void noalloc_state_free(NoAllocState *n) { delete n; }
+}  // namespace qtn
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+extern "C" int qtn_contract_noalloc(qtn_plan_t *P, uint64_t lo, uint64_t hi, uint64_t slices_per_wave,
+                                    void *stream_v, qtn_partial *out_dev) {
+  set_error("");
+  if (!P || !out_dev) {
+    set_error("NULL argument");
+    return QTN_EINVAL;
+  }
+  const uint64_t nslices = 1ull << P->cut.size();
+  if (lo > hi || hi > nslices) {
+    set_error("slice range outside [0, 2^k)");
+    return QTN_ERANGE;
+  }
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  char *base = nullptr;
+  if (int rc = scratch_address(dev, &base)) return rc;
+  hipStream_t stream = (hipStream_t)stream_v;
+  const uint64_t B = P->net.B;
+  NoAllocState *N = P->na;
+  if (!N || N->device != dev || N->S != std::min(slices_per_wave, nslices)) {
+    BindShape shape;
+    if (int rc = bind_shape(P, slices_per_wave, shape)) return rc;
+    std::unique_ptr<NoAllocState> fresh(new NoAllocState());
+    N = fresh.get();
+    N->device = dev;
+    N->S = shape.S;
+    N->base = base;
+    DeviceState &D = N->D;
+    D.device = dev;
+    D.mode = shape.mode;
+    D.L = shape.L;
+    D.max_slots = shape.max_slots;
+    D.lds_bytes = shape.lds_bytes;
+    D.lds_total = shape.lds_total;
+    D.desc_bytes = shape.desc_off;
+    D.use_graphs = false;
+    try {
+      // launch units in schedule order on the caller's stream
+      D.lg = launch_graph(P->sched, P->exec[D.mode], D.L, P->net.B, D.L.S, P->precision != QTN_FP64, 1);
+    } catch (const std::exception &e) {
+      set_error(e.what());
+      return QTN_ESTATE;
+    }
+    N->leaves = leaf_host(P, D.leaf_elem_off);
+    // scratch: gate factors | program descriptors | workspace
+    N->leaf_off = 0;
+    D.leafbuf = base + N->leaf_off;
+    N->blob_off = align256(N->leaf_off + N->leaves.size() * sizeof(double));
+    // the descriptor blob's size does not depend on the addresses it holds
+    D.ws = base;
+    fill_tables(P, &D, P->exec[D.mode], N->blob);
+    N->ws_off = align256(N->blob_off + N->blob.size());
+    N->total = N->ws_off + D.L.total_bytes;
+    if (N->total > kNoAllocBytes) {
+      set_error("qtn_contract_noalloc: this plan needs " + std::to_string(N->total) +
+                " bytes of scratch (gate factors, descriptors, workspace) at " +
+                std::to_string(shape.S) + " slices per wave; the scratch holds " +
+                std::to_string(kNoAllocBytes));
+      return QTN_ENOMEM;
+    }
+    D.ws = base + N->ws_off;
+    D.ws_bytes = D.L.total_bytes;
+    fill_tables(P, &D, P->exec[D.mode], N->blob);
+    delete P->na;
+    P->na = fresh.release();
+  }
+  if (lo == hi) {
+    // exact zeros, written on the stream like every other result
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, stream, (uint32_t *)out_dev,
+                       (uint64_t)(B * sizeof(qtn_partial) / 4));
+    HIP_TRY(hipGetLastError());
+    return QTN_OK;
+  }
+  DeviceState &D = N->D;
+  if (int rc = set_program_lds(D.lds_total)) return rc;
+  // the scratch is shared by every plan on this device: upload this plan's
+  // constants and clear its exponent words on the stream, before its kernels
+  HIP_TRY(hipMemcpyAsync(base + N->leaf_off, N->leaves.data(), N->leaves.size() * sizeof(double),
+                         hipMemcpyHostToDevice, stream));
+  if (!N->blob.empty())
+    HIP_TRY(hipMemcpyAsync(base + N->blob_off, N->blob.data(), N->blob.size(), hipMemcpyHostToDevice, stream));
+  D.blobbuf = base + N->blob_off;
+  const bool scaled = P->precision != QTN_FP64;
+  if (scaled && D.L.exp_bytes) {
+    const uint64_t words = D.L.exp_bytes / 4;
+    const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((words + 255) / 256, 1024));
+    hipLaunchKernelGGL(zero_words, dim3(blocks), dim3(256), 0, stream, (uint32_t *)(D.ws + D.L.data_bytes), words);
+  }
+  D.host_partials_dev = out_dev;   // the last wave's slice sum writes the result here
+  return scaled ? run_waves<true>(P, &D, lo, hi, stream, false) : run_waves<false>(P, &D, lo, hi, stream, false);
+}
+
 extern "C" int qtn_plan_set_graphs(qtn_plan_t *P, int enable) {
   if (!P || !P->dev) {
     set_error("bind a workspace first");

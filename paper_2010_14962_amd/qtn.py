@@ -94,7 +94,7 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search",
            "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_contract_async",
            "qtn_contract_ranges", "qtn_plan_fingerprint", "qtn_plan_inject_faults",
-           "qtn_batch_contract", "qtn_plan_autotune"]
+           "qtn_contract_noalloc", "qtn_batch_contract", "qtn_plan_autotune"]
 COST_FEATURES = 32
 
 
@@ -157,6 +157,7 @@ def lib():
     L.qtn_contract_ranges.argtypes = [c_void_p, c_uint64, c_int32, c_char_p, c_void_p,
                                       POINTER(QtnPartial), POINTER(QtnRangeStats)]
     L.qtn_plan_fingerprint.argtypes = [c_void_p, POINTER(c_uint64)]
+    L.qtn_contract_noalloc.argtypes = [c_void_p, c_uint64, c_uint64, c_uint64, c_void_p, c_void_p]
     L.qtn_plan_autotune.argtypes = [c_void_p, c_void_p, c_char_p, POINTER(QtnTuneStats)]
     L.qtn_batch_contract.argtypes = [POINTER(c_void_p), c_uint32, POINTER(c_uint64), POINTER(c_uint64),
                                      c_void_p, POINTER(QtnPartial)]
@@ -312,6 +313,20 @@ class Plan:
         return [out[i] for i in range(self.n_bitstrings)], {
             "ranges": st.ranges, "contracted": st.contracted, "resumed": st.resumed,
             "retried": st.retried}
+
+    def contract_noalloc(self, slice_lo: int, slice_hi: int, slices_per_wave: int, out_dev: int,
+                         stream: Optional[int] = None) -> None:
+        """Enqueues the contraction using the library's fixed device scratch
+        (no allocation); partials go to device address out_dev."""
+        _check(lib().qtn_contract_noalloc(self._h, slice_lo, slice_hi, slices_per_wave,
+                                          c_void_p(stream or 0), c_void_p(out_dev)))
+
+    def autotune(self, cache: Optional[str] = None, stream: Optional[int] = None) -> dict:
+        """Measures and keeps the launch configuration of each streaming step."""
+        st = QtnTuneStats()
+        _check(lib().qtn_plan_autotune(self._h, c_void_p(stream or 0),
+                                       cache.encode() if cache else None, byref(st)))
+        return {f: getattr(st, f) for f, _ in QtnTuneStats._fields_}
 
     def fingerprint(self) -> int:
         v = c_uint64()
