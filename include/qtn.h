@@ -147,6 +147,28 @@ int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
              uint32_t n_bitstrings, const qtn_plan_opts *opts,
              qtn_plan_t **out);
 
+/*
+ * General circuits (gates that are not diagonal, as in the random circuits of
+ * Sec. IV B): a plan for the amplitudes <x|U_m ... U_1|0^n> of n_bitstrings
+ * bitstrings.  Each gate acts on 1 or 2 qubits with matrix[out][in]
+ * (row-major re/im, 2x2 or 4x4; for two qubits q[0] is the more significant
+ * bit of both indices).  The network (Sec. II A, Fig. 1) has one binary
+ * variable per wire segment: a diagonal gate keeps its wires' variables (its
+ * factor holds the diagonal), any other gate starts new ones; inputs are |0>
+ * and the final variables carry the measured bits.  Cut search, order,
+ * schedule and contraction are those of qtn_plan (k counts wire variables,
+ * slice s fixes cut[b] to bit b of s); density_matrix and use_cost_model are
+ * not available here (QTN_EINVAL).  qtn_plan_info.p is 0.
+ */
+typedef struct {
+  uint32_t nq;        /* 1 or 2                                          */
+  uint32_t q[2];      /* qubits, distinct, < n                           */
+  double re[16];      /* matrix entries, row-major, first 4 or 16 used   */
+  double im[16];
+} qtn_gate;
+int qtn_plan_circuit(uint32_t n, const qtn_gate *gates, uint32_t n_gates, const uint8_t *bitstrings,
+                     uint32_t n_bitstrings, const qtn_plan_opts *opts, qtn_plan_t **out);
+
 /* Frees the plan and the constant device buffers it uploaded (leaf factors,
  * program descriptors, pinned partials); the bound workspace stays the
  * caller's.  NULL is ignored. */

@@ -44,55 +44,15 @@ static int fail(int code, const std::string &msg) {
   return code;
 }
 
-extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
-                        const double *beta, const uint8_t *bitstrings,
-                        uint32_t n_bitstrings, const qtn_plan_opts *opts_in,
-                        qtn_plan_t **out) {
-  set_error("");
-  if (!out) return fail(QTN_EINVAL, "out is NULL");
-  *out = nullptr;
-  qtn_plan_opts opts;
-  if (opts_in)
-    opts = *opts_in;
-  else
-    qtn_plan_opts_default(&opts);
-  if (!graph || !gamma || !beta || !bitstrings)
-    return fail(QTN_EINVAL, "NULL argument");
-  if (graph->n == 0 || (graph->m > 0 && !graph->edges))
-    return fail(QTN_EINVAL, "empty graph");
-  if (p == 0 || p > 64) return fail(QTN_EINVAL, "p must be in [1, 64]");
-  if (n_bitstrings == 0) return fail(QTN_EINVAL, "no bitstrings");
-  if ((uint64_t)graph->n * p > 4096) return fail(QTN_EINVAL, "too many variables");
-  if (opts.precision == QTN_3XBF16)
-    return fail(QTN_EINVAL, "split-BF16 products need dense steps; no step of these schedules is dense");
-  if (opts.precision < QTN_FP64 || opts.precision > QTN_3XBF16)
-    return fail(QTN_EINVAL, "unknown precision");
-  for (uint32_t l = 0; l < p; ++l)
-    if (!std::isfinite(gamma[l]) || !std::isfinite(beta[l]))
-      return fail(QTN_EINVAL, "non-finite angle");
-  std::set<std::pair<uint32_t, uint32_t>> seen;
-  for (uint32_t e = 0; e < graph->m; ++e) {
-    uint32_t a = graph->edges[2 * e], b = graph->edges[2 * e + 1];
-    if (a >= graph->n || b >= graph->n) return fail(QTN_EINVAL, "edge vertex out of range");
-    if (a == b) return fail(QTN_EINVAL, "self-loop");
-    if (a > b) std::swap(a, b);
-    if (!seen.insert({a, b}).second) return fail(QTN_EINVAL, "repeated edge");
-  }
-  for (uint64_t i = 0; i < (uint64_t)n_bitstrings * graph->n; ++i)
-    if (bitstrings[i] > 1) return fail(QTN_EINVAL, "bitstring byte not 0/1");
-
-  qtn_plan_t *P = new (std::nothrow) qtn_plan_t();
-  if (!P) return fail(QTN_ENOMEM, "host allocation");
+// Everything after the network: line graph, cut search (Algorithm 1, or the
+// model-guided search with use_cost_model; for the density-matrix form on
+// the graph of (ket, bra) pairs), min-fill order, schedule, storage and
+// execution plans.  graph and p describe a QAOA network for the cost model
+// (graph NULL for general circuits).  On failure P is freed and the error
+// code returned.
+static int plan_rest(qtn_plan_t *P, const qtn_plan_opts &opts, const qtn_graph *graph, uint32_t p) {
   try {
     Network &net = P->net;
-    net.n = graph->n;
-    net.p = p;
-    net.edges.assign(seen.begin(), seen.end());
-    net.gamma.assign(gamma, gamma + p);
-    net.beta.assign(beta, beta + p);
-    net.B = n_bitstrings;
-    net.bits.assign(bitstrings, bitstrings + (size_t)n_bitstrings * graph->n);
-    build_network(net);
     auto adj = line_graph(net);
     const int V = (int)net.nv;
     auto t0 = std::chrono::steady_clock::now();
@@ -242,6 +202,126 @@ extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
     delete P;
     return fail(QTN_EINVAL, e.what());
   }
+  return QTN_OK;
+}
+
+extern "C" int qtn_plan(const qtn_graph *graph, uint32_t p, const double *gamma,
+                        const double *beta, const uint8_t *bitstrings,
+                        uint32_t n_bitstrings, const qtn_plan_opts *opts_in,
+                        qtn_plan_t **out) {
+  set_error("");
+  if (!out) return fail(QTN_EINVAL, "out is NULL");
+  *out = nullptr;
+  qtn_plan_opts opts;
+  if (opts_in)
+    opts = *opts_in;
+  else
+    qtn_plan_opts_default(&opts);
+  if (!graph || !gamma || !beta || !bitstrings)
+    return fail(QTN_EINVAL, "NULL argument");
+  if (graph->n == 0 || (graph->m > 0 && !graph->edges))
+    return fail(QTN_EINVAL, "empty graph");
+  if (p == 0 || p > 64) return fail(QTN_EINVAL, "p must be in [1, 64]");
+  if (n_bitstrings == 0) return fail(QTN_EINVAL, "no bitstrings");
+  if ((uint64_t)graph->n * p > 4096) return fail(QTN_EINVAL, "too many variables");
+  if (opts.precision == QTN_3XBF16)
+    return fail(QTN_EINVAL, "split-BF16 products need dense steps; no step of these schedules is dense");
+  if (opts.precision < QTN_FP64 || opts.precision > QTN_3XBF16)
+    return fail(QTN_EINVAL, "unknown precision");
+  for (uint32_t l = 0; l < p; ++l)
+    if (!std::isfinite(gamma[l]) || !std::isfinite(beta[l]))
+      return fail(QTN_EINVAL, "non-finite angle");
+  std::set<std::pair<uint32_t, uint32_t>> seen;
+  for (uint32_t e = 0; e < graph->m; ++e) {
+    uint32_t a = graph->edges[2 * e], b = graph->edges[2 * e + 1];
+    if (a >= graph->n || b >= graph->n) return fail(QTN_EINVAL, "edge vertex out of range");
+    if (a == b) return fail(QTN_EINVAL, "self-loop");
+    if (a > b) std::swap(a, b);
+    if (!seen.insert({a, b}).second) return fail(QTN_EINVAL, "repeated edge");
+  }
+  for (uint64_t i = 0; i < (uint64_t)n_bitstrings * graph->n; ++i)
+    if (bitstrings[i] > 1) return fail(QTN_EINVAL, "bitstring byte not 0/1");
+
+  qtn_plan_t *P = new (std::nothrow) qtn_plan_t();
+  if (!P) return fail(QTN_ENOMEM, "host allocation");
+  try {
+    Network &net = P->net;
+    net.n = graph->n;
+    net.p = p;
+    net.edges.assign(seen.begin(), seen.end());
+    net.gamma.assign(gamma, gamma + p);
+    net.beta.assign(beta, beta + p);
+    net.B = n_bitstrings;
+    net.bits.assign(bitstrings, bitstrings + (size_t)n_bitstrings * graph->n);
+    build_network(net);
+    if (int rc = plan_rest(P, opts, graph, p)) return rc;   // frees P on failure
+  } catch (const std::bad_alloc &) {
+    delete P;
+    return fail(QTN_ENOMEM, "host allocation");
+  } catch (const std::exception &e) {
+    delete P;
+    return fail(QTN_EINVAL, e.what());
+  }
+  *out = P;
+  return QTN_OK;
+}
+
+extern "C" int qtn_plan_circuit(uint32_t n, const qtn_gate *gates, uint32_t n_gates,
+                                const uint8_t *bitstrings, uint32_t n_bitstrings,
+                                const qtn_plan_opts *opts_in, qtn_plan_t **out) {
+  set_error("");
+  if (!out) return fail(QTN_EINVAL, "out is NULL");
+  *out = nullptr;
+  qtn_plan_opts opts;
+  if (opts_in)
+    opts = *opts_in;
+  else
+    qtn_plan_opts_default(&opts);
+  if (n == 0 || n > 4096 || !bitstrings || (n_gates && !gates)) return fail(QTN_EINVAL, "NULL argument or no qubits");
+  if (n_bitstrings == 0) return fail(QTN_EINVAL, "no bitstrings");
+  if (opts.precision == QTN_3XBF16)
+    return fail(QTN_EINVAL, "split-BF16 products need dense steps; no step of these schedules is dense");
+  if (opts.precision < QTN_FP64 || opts.precision > QTN_3XBF16) return fail(QTN_EINVAL, "unknown precision");
+  if (opts.density_matrix) return fail(QTN_EINVAL, "the density-matrix form is built for QAOA plans only");
+  if (opts.use_cost_model) return fail(QTN_EINVAL, "the cost model is trained on QAOA networks only");
+  std::vector<GateSpec> gs(n_gates);
+  for (uint32_t g = 0; g < n_gates; ++g) {
+    const qtn_gate &G = gates[g];
+    if (G.nq < 1 || G.nq > 2) return fail(QTN_EINVAL, "gate " + std::to_string(g) + ": 1 or 2 qubits");
+    for (uint32_t j = 0; j < G.nq; ++j)
+      if (G.q[j] >= n) return fail(QTN_EINVAL, "gate " + std::to_string(g) + ": qubit out of range");
+    if (G.nq == 2 && G.q[0] == G.q[1]) return fail(QTN_EINVAL, "gate " + std::to_string(g) + ": repeated qubit");
+    const int d = 1 << G.nq;
+    gs[g].nq = (int)G.nq;
+    gs[g].q[0] = (int)G.q[0];
+    gs[g].q[1] = G.nq > 1 ? (int)G.q[1] : -1;
+    gs[g].m.resize((size_t)d * d);
+    for (int i = 0; i < d * d; ++i) {
+      if (!std::isfinite(G.re[i]) || !std::isfinite(G.im[i]))
+        return fail(QTN_EINVAL, "gate " + std::to_string(g) + ": non-finite matrix entry");
+      gs[g].m[i] = cd(G.re[i], G.im[i]);
+    }
+  }
+  for (uint64_t i = 0; i < (uint64_t)n_bitstrings * n; ++i)
+    if (bitstrings[i] > 1) return fail(QTN_EINVAL, "bitstring byte not 0/1");
+  qtn_plan_t *P = new (std::nothrow) qtn_plan_t();
+  if (!P) return fail(QTN_ENOMEM, "host allocation");
+  try {
+    Network &net = P->net;
+    net.n = n;
+    net.p = 0;
+    net.B = n_bitstrings;
+    net.bits.assign(bitstrings, bitstrings + (size_t)n_bitstrings * n);
+    build_circuit_network(net, gs);
+    if (net.nv > 4096) {
+      delete P;
+      return fail(QTN_EINVAL, "too many wire variables");
+    }
+  } catch (const std::bad_alloc &) {
+    delete P;
+    return fail(QTN_ENOMEM, "host allocation");
+  }
+  if (int rc = plan_rest(P, opts, nullptr, 0)) return rc;   // frees P on failure
   *out = P;
   return QTN_OK;
 }

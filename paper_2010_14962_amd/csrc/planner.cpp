@@ -93,6 +93,59 @@ void build_network(Network &net) {
   }
 }
 
+void build_circuit_network(Network &net, const std::vector<GateSpec> &gates) {
+  const uint32_t n = net.n;
+  net.factors.clear();
+  net.values.clear();
+  std::vector<int> wire(n);
+  int nv = 0;
+  for (uint32_t q = 0; q < n; ++q) {
+    wire[q] = nv++;
+    net.factors.push_back(Factor{1, {wire[q], -1, -1, -1}, 0, 0, (int)q});
+    net.values.push_back({cd(1.0, 0.0), cd(0.0, 0.0)});   // |0>
+  }
+  for (size_t g = 0; g < gates.size(); ++g) {
+    const GateSpec &G = gates[g];
+    const int d = 1 << G.nq;
+    bool diag = true;
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c)
+        if (r != c && G.m[(size_t)r * d + c] != cd(0.0, 0.0)) diag = false;
+    if (diag) {
+      // a diagonal gate leaves the wire values unchanged: one factor on the
+      // current variables holding the diagonal
+      Factor f{G.nq, {wire[G.q[0]], G.nq > 1 ? wire[G.q[1]] : -1, -1, -1}, 0, (int)g, G.q[0]};
+      std::vector<cd> v(d);
+      for (int r = 0; r < d; ++r) v[r] = G.m[(size_t)r * d + r];
+      net.factors.push_back(f);
+      net.values.push_back(v);
+    } else {
+      Factor f{2 * G.nq, {-1, -1, -1, -1}, 0, (int)g, G.q[0]};
+      for (int j = 0; j < G.nq; ++j) f.v[G.nq + j] = wire[G.q[j]];   // inputs
+      for (int j = 0; j < G.nq; ++j) {
+        wire[G.q[j]] = nv++;
+        f.v[j] = wire[G.q[j]];                                          // outputs
+      }
+      // index bits: outputs (first qubit most significant), then inputs
+      net.factors.push_back(f);
+      net.values.push_back(G.m);
+    }
+  }
+  for (uint32_t q = 0; q < n; ++q) {
+    Factor f{1, {wire[q], -1, -1, -1}, 2, 0, (int)q};
+    std::vector<cd> v(2 * net.B);
+    for (uint32_t b = 0; b < net.B; ++b) {
+      const int x = net.bits[(size_t)b * n + q];
+      v[b * 2 + 0] = cd(x == 0 ? 1.0 : 0.0, 0.0);
+      v[b * 2 + 1] = cd(x == 1 ? 1.0 : 0.0, 0.0);
+    }
+    net.factors.push_back(f);
+    net.values.push_back(v);
+  }
+  net.nv = (uint32_t)nv;
+  net.prefactor = 1.0;
+}
+
 std::vector<std::vector<int>> line_graph(const Network &net) {
   std::vector<std::vector<int>> adj(net.nv);
   for (auto &f : net.factors)

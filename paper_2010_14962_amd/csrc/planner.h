@@ -51,6 +51,21 @@ struct Network {
 // Build factors, values and the normalisation prefactor.
 void build_network(Network &net);
 
+// A gate of a general circuit: matrix[out][in] (row-major), 2x2 or 4x4; for
+// two qubits q[0] is the more significant bit of both indices.
+struct GateSpec {
+  int nq;
+  int q[2];
+  std::vector<cd> m;
+};
+
+// Network of a general circuit on |0^n> measured in bitstrings net.bits
+// (net.n qubits, net.B bitstrings): one binary variable per wire segment;
+// a diagonal gate keeps its wires' variables (its factor holds the diagonal),
+// any other gate starts new ones.  Factors: |0> on every input variable, the
+// gate tensors, and the measured value of every final variable.
+void build_circuit_network(Network &net, const std::vector<GateSpec> &gates);
+
 // Line graph (variable interaction graph), Sec. II B; adjacency lists sorted.
 std::vector<std::vector<int>> line_graph(const Network &net);
 

@@ -45,6 +45,7 @@ static uint64_t fingerprint(const qtn_plan_t *P) {
   mix(N.gamma.data(), N.gamma.size() * sizeof(double));
   mix(N.beta.data(), N.beta.size() * sizeof(double));
   mix(N.bits.data(), N.bits.size());
+  for (const auto &v : N.values) mix(v.data(), v.size() * sizeof(cd));   // every gate tensor
   for (int c : P->cut) mix(&c, sizeof c);
   mix(&P->precision, sizeof P->precision);
   return h;

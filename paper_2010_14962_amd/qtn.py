@@ -71,6 +71,10 @@ class QtnRangeStats(ctypes.Structure):
                 ("retried", c_uint64)]
 
 
+class QtnGate(ctypes.Structure):
+    _fields_ = [("nq", c_uint32), ("q", c_uint32 * 2), ("re", c_double * 16), ("im", c_double * 16)]
+
+
 class QtnTuneStats(ctypes.Structure):
     _fields_ = [("steps", c_uint32), ("measured", c_uint32), ("cached", c_uint32),
                 ("default_us", c_double), ("tuned_us", c_double)]
@@ -94,7 +98,7 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search",
            "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_contract_async",
            "qtn_contract_ranges", "qtn_plan_fingerprint", "qtn_plan_inject_faults",
-           "qtn_contract_noalloc", "qtn_batch_contract", "qtn_plan_autotune"]
+           "qtn_contract_noalloc", "qtn_batch_contract", "qtn_plan_autotune", "qtn_plan_circuit"]
 COST_FEATURES = 32
 
 
@@ -158,6 +162,8 @@ def lib():
                                       POINTER(QtnPartial), POINTER(QtnRangeStats)]
     L.qtn_plan_fingerprint.argtypes = [c_void_p, POINTER(c_uint64)]
     L.qtn_contract_noalloc.argtypes = [c_void_p, c_uint64, c_uint64, c_uint64, c_void_p, c_void_p]
+    L.qtn_plan_circuit.argtypes = [c_uint32, POINTER(QtnGate), c_uint32, POINTER(c_uint8), c_uint32,
+                                   POINTER(QtnPlanOpts), POINTER(c_void_p)]
     L.qtn_plan_autotune.argtypes = [c_void_p, c_void_p, c_char_p, POINTER(QtnTuneStats)]
     L.qtn_batch_contract.argtypes = [POINTER(c_void_p), c_uint32, POINTER(c_uint64), POINTER(c_uint64),
                                      c_void_p, POINTER(QtnPartial)]
@@ -385,6 +391,40 @@ def qtn_partial_combine(a: QtnPartial, b: QtnPartial) -> QtnPartial:
     out = QtnPartial()
     _check(lib().qtn_partial_combine(byref(a), byref(b), byref(out)))
     return out
+
+
+def qtn_plan_circuit(n: int, gates, bitstrings, k: int = -1, max_rank: int = 0, k_max: int = 24,
+                     cut_vars: Optional[Sequence[int]] = None, seed: int = 0, ga_pop: int = 11,
+                     ga_iters: int = 4, precision: str = "fp64", fuse_chains: bool = True,
+                     exec_mode: str = "auto") -> Plan:
+    """Plan for a general circuit: gates are (qubits, matrix[out][in]) pairs."""
+    L = lib()
+    arr = (QtnGate * max(1, len(gates)))()
+    for i, (qs, U) in enumerate(gates):
+        U = np.asarray(U, dtype=np.complex128).reshape(-1)
+        arr[i].nq = len(qs)
+        for j, q in enumerate(qs):
+            arr[i].q[j] = int(q)
+        for j, v in enumerate(U):
+            arr[i].re[j] = float(v.real)
+            arr[i].im[j] = float(v.imag)
+    bits = np.ascontiguousarray(np.asarray(bitstrings, dtype=np.uint8).reshape(-1, n))
+    opts = QtnPlanOpts()
+    L.qtn_plan_opts_default(byref(opts))
+    opts.k, opts.max_rank, opts.k_max, opts.seed = k, max_rank, k_max, seed
+    opts.ga_pop, opts.ga_iters = ga_pop, ga_iters
+    opts.precision = PRECISIONS[precision]
+    opts.fuse_chains = 1 if fuse_chains else 0
+    opts.exec_mode = {"auto": -1, "wide": 0, "slice": 1}[exec_mode]
+    cv = None
+    if cut_vars is not None:
+        cv = _u32(cut_vars)
+        opts.k = len(cv)
+        opts.cut_vars = cv.ctypes.data_as(POINTER(c_uint32))
+    h = c_void_p()
+    _check(L.qtn_plan_circuit(n, arr, len(gates), bits.ctypes.data_as(POINTER(c_uint8)), bits.shape[0],
+                              byref(opts), byref(h)))
+    return Plan(h.value, n, bits.shape[0])
 
 
 def batch_contract(plans: Sequence["Plan"], ranges: Sequence[tuple], stream: Optional[int] = None):
