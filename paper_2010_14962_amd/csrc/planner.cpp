@@ -611,6 +611,11 @@ int assign_storage(Schedule &s, int precision, double small_share) {
   double acc = 0.0;
   while (R < 63 && acc + by_rank[R] <= small_share * total) acc += by_rank[R++];
   R = std::max(R, kAlwaysF64Rank);
+  static const int env_rank = [] {
+    const char *e = std::getenv("QTN_F64_RANK");  // tuning switch: tensors below this rank stay complex128
+    return e ? std::atoi(e) : 0;
+  }();
+  R = std::max(R, env_rank);
   for (auto &t : s.tensors) t.f64 = t.leaf || t.rank() < R;
   return R;
 }
@@ -1132,6 +1137,11 @@ LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, 
       for (size_t a = 0; a < U; ++a)
         if (anc[u][a]) anc[v][a] = 1;
     }
+  }
+  G.level.assign(U, 0);
+  for (size_t v = 0; v < U; ++v) {
+    for (int u : G.deps[v]) G.level[v] = std::max(G.level[v], G.level[u] + 1);
+    G.nlevels = std::max(G.nlevels, G.level[v] + 1);
   }
   // enqueue order: among ready units, the one with the longest remaining
   // path first, a unit weighing a fixed launch latency plus its bytes

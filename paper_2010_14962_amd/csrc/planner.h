@@ -259,6 +259,10 @@ struct LaunchGraph {
   std::vector<char> record;            // another stream waits for this unit
   std::vector<int> order;              // enqueue order: a topological order, longest remaining path first
   int nstreams = 1;
+  // longest dependency path from a unit without dependencies: units of one
+  // level never depend on each other and may run in one launch
+  std::vector<int> level;
+  int nlevels = 0;
 };
 LaunchGraph launch_graph(const Schedule &s, const ExecPlan &x, const Layout &L, uint64_t B,
                          uint64_t S, bool scaled, int max_streams);

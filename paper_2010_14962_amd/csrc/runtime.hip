@@ -182,6 +182,9 @@ struct DeviceState {
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kSide] = {nullptr, nullptr, nullptr};
   int max_streams = 1 + kSide;
+  // launch units level by level, independent steps of a level in one
+  // step_multi launch (QTN_LEVELS=0: side streams under graph capture)
+  bool levels = true;
   // captured launch sequence of one slice range, replayed while it matches
   bool use_graphs = true;
   hipStream_t gstream = nullptr;
@@ -852,6 +855,61 @@ struct InstanceSetup {
   uint64_t obase;
 };
 
+// The same set-up done by a whole block.  setup_begin issues every load at
+// once: thread t reads slot word t % 32 of input t / 32 (and the exponent
+// word of that input), the 32 slot words of an input are reduced within the
+// wave, so that all rescaled inputs cost one memory round trip instead of
+// one each.  After a barrier, setup_end adds the shifts from LDS.  The block
+// must not rewrite S before every thread has passed setup_end.
+struct SetupLds {
+  uint32_t m[kMaxIn];   // slot maximum of each input (0: not rescaled)
+  int e[kMaxIn];        // exponent word of each input
+};
+template <bool SCALE>
+__device__ __forceinline__ void setup_begin(const PStep &d, uint32_t ns, uint64_t q, uint64_t s_lo,
+                                            InstanceSetup &I, SetupLds &S) {
+  const uint32_t b = (uint32_t)(q / ns);
+  const uint32_t sl = (uint32_t)(q - (uint64_t)b * ns);
+  const uint32_t s = (uint32_t)(s_lo + sl);
+  I.sh = 0;
+  I.esum = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxIn; ++i)
+    if (i < d.nin) I.off[i] = inst_off(d.in[i], b, sl, s);
+  I.qo = b * d.out.ebstride + sl * d.out.esstride;
+  I.obase = (uint64_t)b * d.out.bstride + (uint64_t)sl * d.out.sstride;
+  if (SCALE) {
+    static_assert(kMaxIn * kMaxSlots <= 256, "one thread per slot word");
+    const uint32_t t = threadIdx.x, i = t / kMaxSlots, k = t % kMaxSlots;
+    uint32_t w = 0;
+    int e = 0;
+    if (i < (uint32_t)d.nin && d.in[i].loc == LOC_GLOBAL) {
+      const OpDesc &in = d.in[i];
+      const uint32_t qi = b * in.ebstride + sl * in.esstride;
+      w = in.M[(uint64_t)qi * kMaxSlots + k];
+      if (k == 0) e = in.E[qi];
+    }
+#pragma unroll
+    for (int o = kMaxSlots / 2; o > 0; o >>= 1) w = max(w, (uint32_t)__shfl_xor((int)w, o, kMaxSlots));
+    if (k == 0 && i < (uint32_t)kMaxIn) {
+      S.m[i] = w;
+      S.e[i] = e;
+    }
+  }
+}
+template <bool SCALE>
+__device__ __forceinline__ void setup_end(const PStep &d, InstanceSetup &I, const SetupLds &S) {
+  if (SCALE) {
+#pragma unroll
+    for (int i = 0; i < kMaxIn; ++i)
+      if (i < d.nin) {
+        const int x = exp_of_bits(S.m[i]);   // 0 for inputs that are not rescaled
+        I.sh += x;
+        I.esum += S.e[i] + x;
+      }
+  }
+}
+
 template <bool SCALE>
 __device__ __forceinline__ void setup_instance(const PStep &d, uint32_t ns, uint64_t q,
                                                uint64_t s_lo, InstanceSetup &I) {
@@ -891,15 +949,16 @@ __device__ __forceinline__ double2 grid_point(const PStep &d, const uint64_t *ci
 }
 
 // Streaming steps (output of >= 2^kStreamMinRank elements per instance).
-// blockIdx.y walks the instances; each x-block owns chunks of 4096
+// The block's y coordinate walks the instances; each x-block owns chunks of 4096
 // consecutive output elements.  Thread t always handles elements with low
 // bits t, so its per-lane index part is fixed; the mid/high parts and the
 // kappa offsets are block-uniform and come from LDS.  Operands that do not
 // depend on the output element (gate factors on summed variables) are folded
 // into one coefficient per kappa value, computed once per instance.
 template <bool SCALE, int NK, int NV, int NF>
-__global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, uint32_t ns,
-                                                   uint64_t s_lo, uint32_t jspan) {
+__device__ __forceinline__ void stream_body(const PStep &d, uint32_t nb, uint32_t ns, uint64_t s_lo,
+                                            uint32_t jspan, uint32_t bx, uint32_t by, uint32_t gx,
+                                            uint32_t gy) {
   constexpr uint32_t NKAP = 1u << NK;
   __shared__ uint32_t s_mid[NV][16];
   __shared__ uint32_t s_kap[NV][NKAP];
@@ -928,14 +987,14 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
   if (dot) dot_args_to_lds((const DotArgs *)d.dotp, DA);
   double2 *dsw = dot ? dsv + DA->nvals : nullptr;
   DotState DS;
-  for (uint64_t q = blockIdx.y; q < Q; q += gridDim.y) {
+  __shared__ SetupLds SL;
+  for (uint64_t q = by; q < Q; q += gy) {
     InstanceSetup I;
-    setup_instance<SCALE>(d, ns, q, s_lo, I);
+    setup_begin<SCALE>(d, ns, q, s_lo, I, SL);
     if (dot) {
       const uint32_t b = (uint32_t)(q / ns);
       dot_begin(DA, b, (uint32_t)(s_lo + (q - (uint64_t)b * ns)), dsv, DS);
     }
-    __syncthreads();
     if (t < NKAP) {
       double2 c = make_double2(1.0, 0.0);
 #pragma unroll
@@ -944,6 +1003,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
       s_coef[t] = c;
     }
     __syncthreads();
+    setup_end<SCALE>(d, I, SL);
     // per-lane operand pointers for this instance; in[0..NF) are in the 64-bit form
     const char *vp[NV];
 #pragma unroll
@@ -953,7 +1013,7 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
     const uint32_t of = d.out.f64;
     const int sh = I.sh;
     uint32_t wmax = 0;
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    for (uint32_t u = bx; u < units; u += gx) {
       const uint32_t j0 = u * jspan;            // in units of 256 elements
       if (dot) dot_rows(DA, dsv, j0, jspan, dsw);
       uint32_t hoff[NV];
@@ -1016,17 +1076,24 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
       }
     }
     if (dot) {
-      dot_end(DA, DS, I.qo, blockIdx.x, dsw + 32);
-      if (SCALE && t == 0 && blockIdx.x == 0) d.out.E[I.qo] = I.esum;
+      dot_end(DA, DS, I.qo, bx, dsw + 32);
+      if (SCALE && t == 0 && bx == 0) d.out.E[I.qo] = I.esum;
     } else if (SCALE) {
       // every thread of the block ran the same trips
       const uint32_t m = block_max(wmax, red4);
       if (t == 0) {
-        raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots + (blockIdx.x % kMaxSlots), m);
-        if (blockIdx.x == 0) d.out.E[I.qo] = I.esum;
+        raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots + (bx % kMaxSlots), m);
+        if (bx == 0) d.out.E[I.qo] = I.esum;
       }
     }
+    __syncthreads();  // s_coef and SL are rewritten for the next instance
   }
+}
+
+template <bool SCALE, int NK, int NV, int NF>
+__global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, uint32_t ns,
+                                                   uint64_t s_lo, uint32_t jspan) {
+  stream_body<SCALE, NK, NV, NF>(d, nb, ns, s_lo, jspan, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
 }
 
 // Streaming steps whose varying operands are re-read many times per row.
@@ -1037,8 +1104,9 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
 // those runs in LDS once per row and sums over kappa from LDS, so each
 // operand element is fetched once per row instead of once per use.
 template <bool SCALE, int NK, int NV, int NF, bool FOLD>
-__global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, uint32_t ns,
-                                                  uint64_t s_lo, uint32_t jspan) {
+__device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t ns, uint64_t s_lo,
+                                           uint32_t jspan, uint32_t bx, uint32_t by, uint32_t gx,
+                                           uint32_t gy) {
   constexpr uint32_t NKAP = 1u << NK;
   extern __shared__ __align__(16) char stage[];
   __shared__ uint32_t s_mid[NV][16];
@@ -1089,14 +1157,14 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
   if (dot) dot_args_to_lds((const DotArgs *)d.dotp, DA);
   double2 *dsw = dot ? dsv + DA->nvals : nullptr;
   DotState DS;
-  for (uint64_t q = blockIdx.y; q < Q; q += gridDim.y) {
+  __shared__ SetupLds SL;
+  for (uint64_t q = by; q < Q; q += gy) {
     InstanceSetup I;
-    setup_instance<SCALE>(d, ns, q, s_lo, I);
+    setup_begin<SCALE>(d, ns, q, s_lo, I, SL);
     if (dot) {
       const uint32_t b = (uint32_t)(q / ns);
       dot_begin(DA, b, (uint32_t)(s_lo + (q - (uint64_t)b * ns)), dsv, DS);
     }
-    __syncthreads();
     if (t < NKAP) {
       double2 c = make_double2(1.0, 0.0);
 #pragma unroll
@@ -1105,6 +1173,8 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
       s_coef[t] = c;
       s_coefl[perm(t)] = c;
     }
+    __syncthreads();
+    setup_end<SCALE>(d, I, SL);
     char *op = (char *)d.out.base + I.obase * (d.out.f64 ? 16u : 8u);
     const uint32_t of = d.out.f64;
     const int sh = I.sh;
@@ -1135,7 +1205,7 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
       }
       return cfma(head(k, v), opnd(v, k), acc);
     };
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    for (uint32_t u = bx; u < units; u += gx) {
       if (dot) dot_rows(DA, dsv, u * jspan, jspan, dsw);
       // operand bases of the current chunk of 16 rows: instance offset plus
       // the index part of the row bits above the lowest four
@@ -1220,16 +1290,81 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
       }
     }
     if (dot) {
-      dot_end(DA, DS, I.qo, blockIdx.x, dsw + 32);
-      if (SCALE && t == 0 && blockIdx.x == 0) d.out.E[I.qo] = I.esum;
+      dot_end(DA, DS, I.qo, bx, dsw + 32);
+      if (SCALE && t == 0 && bx == 0) d.out.E[I.qo] = I.esum;
     } else if (SCALE) {
       const uint32_t m = block_max(wmax, red4);
       if (t == 0) {
-        raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots + (blockIdx.x % kMaxSlots), m);
-        if (blockIdx.x == 0) d.out.E[I.qo] = I.esum;
+        raise_max(d.out.M + (uint64_t)I.qo * kMaxSlots + (bx % kMaxSlots), m);
+        if (bx == 0) d.out.E[I.qo] = I.esum;
       }
     }
     __syncthreads();  // s_coef and the stage are rewritten for the next instance
+  }
+}
+
+template <bool SCALE, int NK, int NV, int NF, bool FOLD>
+__global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, uint32_t ns,
+                                                  uint64_t s_lo, uint32_t jspan) {
+  tiled_body<SCALE, NK, NV, NF, FOLD>(d, nb, ns, s_lo, jspan, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+}
+
+// Several independent streaming steps in one launch.  The steps of one
+// level of the launch graph (no path between any two of them) are often
+// each too small to fill the chip; run back to back they leave it idle
+// between launches, and on separate streams each join costs a few
+// microseconds.  Here each member owns a contiguous range of the launch's
+// blocks and runs as its own kernel would, with its block coordinates
+// taken from that range.  The member kernels are the common shapes of the
+// mid-size steps (1 or 2 summed variables, 2 or 3 varying operands, at most
+// one of them in the 64-bit form); other steps launch on their own.
+constexpr int kMaxMulti = 4;
+struct MultiArgs {
+  PStep step[kMaxMulti];
+  uint32_t n;
+  uint32_t vid[kMaxMulti];       // member shape (multi_variant)
+  uint32_t blk_end[kMaxMulti];   // cumulative block counts
+  uint32_t gx[kMaxMulti];        // the member's x extent (y = blocks / gx)
+  uint32_t nb[kMaxMulti], ns[kMaxMulti], jspan[kMaxMulti];
+  uint64_t s_lo;
+};
+
+// id = ((tiled * 2 + NK - 1) * 2 + NV - 2) * 2 + NF.  The kernel needs the
+// registers of its largest member; the streaming shapes with more loads in
+// flight (2 summed variables or 3 varying operands) would lower the
+// occupancy of all the others and launch on their own.
+#define QTN_MULTI_SHAPES(X)                                                                        \
+  X(0, 1, 2, 0) X(0, 1, 2, 1) X(1, 1, 2, 0) X(1, 1, 2, 1) X(1, 1, 3, 0) X(1, 1, 3, 1) X(1, 2, 2, 0) \
+  X(1, 2, 2, 1) X(1, 2, 3, 0) X(1, 2, 3, 1)
+
+template <bool SCALE>
+__global__ __launch_bounds__(256) void step_multi(const MultiArgs args) {
+  // the arguments are read in place (the first kernel argument starts the
+  // kernel-argument segment): indexing the by-value copy with the member
+  // number would make a private copy of all of it
+  const MultiArgs &a = *(const MultiArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+  (void)args;
+  const uint32_t blk = blockIdx.x;
+  uint32_t m = 0;
+  while (m + 1 < a.n && blk >= a.blk_end[m]) ++m;
+  const uint32_t local = blk - (m ? a.blk_end[m - 1] : 0u);
+  const uint32_t gx = a.gx[m];
+  const uint32_t gy = (a.blk_end[m] - (m ? a.blk_end[m - 1] : 0u)) / gx;
+  const uint32_t bx = local % gx, by = local / gx;
+  const PStep &d = a.step[m];
+  switch (a.vid[m]) {
+#define QTN_MULTI_CASE(T, K, V, F)                                                                 \
+  case ((T * 2 + K - 1) * 2 + V - 2) * 2 + F:                                                      \
+    if constexpr (SCALE || F == 0) {                                                               \
+      if constexpr (T)                                                                             \
+        tiled_body<SCALE, K, V, F, true>(d, a.nb[m], a.ns[m], a.s_lo, a.jspan[m], bx, by, gx, gy); \
+      else                                                                                         \
+        stream_body<SCALE, K, V, F>(d, a.nb[m], a.ns[m], a.s_lo, a.jspan[m], bx, by, gx, gy);      \
+    }                                                                                              \
+    break;
+    QTN_MULTI_SHAPES(QTN_MULTI_CASE)
+#undef QTN_MULTI_CASE
+    default: break;
   }
 }
 
@@ -1782,7 +1917,6 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   }
   BindShape shape;
   if (int rc = bind_shape(P, S_req, shape)) return rc;
-  const uint64_t S = shape.S;
   const int mode = shape.mode;
   const Layout &L = shape.L;
   const ExecPlan &X = P->exec[mode];
@@ -1833,8 +1967,13 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     D->unit_ev.push_back(e);
   }
+  static const bool env_levels = [] {
+    const char *e = std::getenv("QTN_LEVELS");  // tuning switch: 0 uses side streams
+    return !(e && e[0] == '0');
+  }();
   drop_graph(D);
   D->lg = lg;
+  D->levels = env_levels;
   D->mode = mode;
   D->ws = (char *)dev_ptr;
   D->ws_bytes = bytes;
@@ -1931,6 +2070,86 @@ static void launch_stream(const PStep &d, dim3 grid, hipStream_t stream, uint32_
   }
 }
 
+// Grid of a streaming step over Q instances: units of jspan rows of 256
+// elements (jspan <= 32), about `target` blocks in all.
+static dim3 stream_grid(const PStep &d, uint64_t Q, uint64_t target, uint32_t *jspan_out) {
+  const uint32_t rows = (1u << d.rC) >> 8;
+  uint32_t jspan = 32;
+  while (jspan > 1 && (uint64_t)(rows / jspan) * Q < target) jspan >>= 1;
+  const uint64_t units = rows / jspan;
+  const uint64_t want = std::max<uint64_t>(1, 2 * target / std::max<uint64_t>(Q, 1));
+  *jspan_out = jspan;
+  return dim3((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
+}
+
+// Shape id of a step that step_multi can run (QTN_MULTI_SHAPES), or -1.
+static int multi_shape(const PStep &d, bool scale, bool stream_only) {
+  const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
+  if (!streaming || d.dot) return -1;
+  const bool tiled = d.tiled_lds != 0 && !stream_only;
+  if (tiled && d.tiled_fold != 0) return -1;
+  if (d.nk < 1 || d.nk > 2 || d.nvary < 2 || d.nvary > 3 || d.nf32 > 1) return -1;
+  if (!tiled && (d.nk != 1 || d.nvary != 2)) return -1;
+  if (!scale && d.nf32) return -1;
+  return (((tiled ? 1 : 0) * 2 + d.nk - 1) * 2 + d.nvary - 2) * 2 + d.nf32;
+}
+
+// Blocks per member of a shared launch: QTN_MULTI_TARGET, else half the
+// step's own target (on the n=120 levels of 2 to 4 steps: 512 per member
+// 0.244 ms per contraction, 1024 0.254, 256 0.260, 2048 0.283).
+static uint64_t multi_target(const StepTune &tu) {
+  static const long env = [] {
+    const char *e = std::getenv("QTN_MULTI_TARGET");  // tuning switch
+    return e ? std::atol(e) : 0L;
+  }();
+  return env > 0 ? (uint64_t)env : std::max<uint64_t>(64, tu.target / 2);
+}
+
+// One step_multi launch of the launch units units[0..n) (grid-wide steps of
+// one level, each with a multi_shape).
+template <bool SCALE>
+static int launch_multi(const qtn_plan_t *P, const DeviceState *D, const int *units, size_t n,
+                        hipStream_t stream, uint64_t s_lo, uint64_t cnt) {
+  const ExecPlan &X = P->exec[D->mode];
+  const Schedule &sch = P->sched;
+  MultiArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.n = (uint32_t)n;
+  a.s_lo = s_lo;
+  uint64_t blocks = 0;
+  uint32_t lds = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const int st = X.launches[(size_t)(units[i] - 1)].step;
+    const StepTune tu = D->tune.empty() ? StepTune() : D->tune[st];
+    PStep d = D->steps[st];
+    if (tu.stream_only) d.tiled_lds = 0;
+    const int vid = multi_shape(d, SCALE, false);
+    if (vid < 0) {
+      set_error("internal: step without a shared-launch shape");
+      return QTN_ESTATE;
+    }
+    const uint32_t nb = sch.steps[st].bdep ? (uint32_t)P->net.B : 1;
+    const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
+    uint32_t jspan = 1;
+    const dim3 g = stream_grid(d, (uint64_t)nb * ns, multi_target(tu), &jspan);
+    a.step[i] = d;
+    a.vid[i] = (uint32_t)vid;
+    a.gx[i] = g.x;
+    a.nb[i] = nb;
+    a.ns[i] = ns;
+    a.jspan[i] = jspan;
+    blocks += (uint64_t)g.x * g.y;
+    a.blk_end[i] = (uint32_t)blocks;
+    lds = std::max(lds, d.tiled_lds);
+  }
+  if (blocks == 0 || blocks > 0x7fffffffull) {
+    set_error("internal: shared launch size");
+    return QTN_ESTATE;
+  }
+  hipLaunchKernelGGL((step_multi<SCALE>), dim3((unsigned)blocks), dim3(256), lds, stream, a);
+  return QTN_OK;
+}
+
 // Launches grid-wide step `st` for the wave of `cnt` slices starting at
 // s_lo.  Streaming steps: units of jspan x 256 elements, about tu.target
 // blocks over the chip, each walking up to 32 rows, so that the per-block
@@ -1957,13 +2176,8 @@ static int launch_grid_step(const qtn_plan_t *P, const DeviceState *D, int st, h
     return QTN_ESTATE;
   }
   if (streaming) {
-    const uint64_t target = tu.target;
-    const uint32_t rows = (1u << d.rC) >> 8;
-    uint32_t jspan = 32;
-    while (jspan > 1 && (uint64_t)(rows / jspan) * Q < target) jspan >>= 1;
-    const uint64_t units = rows / jspan;
-    const uint64_t want = std::max<uint64_t>(1, 2 * target / std::max<uint64_t>(Q, 1));
-    const dim3 grid((unsigned)std::min<uint64_t>(units, want), (unsigned)std::min<uint64_t>(Q, 65535));
+    uint32_t jspan = 1;
+    const dim3 grid = stream_grid(d, Q, tu.target, &jspan);
     if (d.dot && dot_gx) *dot_gx = grid.x;
     launch_stream<SCALE>(d, grid, stream, nb, ns, s_lo, jspan);
   } else {
@@ -1990,21 +2204,147 @@ static int run_waves(qtn_plan_t *P, DeviceState *D, uint64_t lo, uint64_t hi, hi
   const uint64_t scratch_stride = (X.scratch_per_wg + 255) & ~uint64_t(255);
   bool first = true;
   const LaunchGraph &lg = D->lg;
-  // Side streams are used only while a graph is being captured: the graph
-  // then holds the launch graph's edges.  Direct launches, and any launch
-  // sequence with timing on, run on `stream` in the enqueue order.
-  const bool multi = concurrent && lg.nstreams > 1 && !D->timing;
+  // Without timing, the launch units run level by level on `stream`, the
+  // eligible steps of one level in shared launches (step_multi).  With
+  // QTN_LEVELS=0, side streams are used instead while a graph is being
+  // captured (the graph then holds the launch graph's edges).  Any launch
+  // sequence with timing on runs on `stream` in the enqueue order.
+  const bool levels = D->levels && !D->timing && lg.nlevels > 0;
+  const bool multi = !levels && concurrent && lg.nstreams > 1 && !D->timing;
   auto unit_stream = [&](int u) {
     return (!multi || lg.stream[u] == 0) ? stream : D->side[lg.stream[u] - 1];
   };
   for (uint64_t s_lo = lo; s_lo < hi; s_lo += S) {
     const uint64_t cnt = std::min<uint64_t>(S, hi - s_lo);
+    const int U = (int)lg.deps.size();
+    auto launch_unit = [&](int u, hipStream_t stream) -> int {
+      if (u == 0) {
+        // exponents were cleared at bind time or by the previous slice sum
+      } else if (u == U - 1) {
+        const uint64_t rb = res.bdep ? (res.sdep ? S : 1) : 0, rs = res.sdep ? 1 : 0;
+        hipLaunchKernelGGL((slice_sum<SCALE>), dim3((unsigned)B), dim3(256), 0, stream,
+                           (const void *)(D->ws + res.data_off), res.f64 ? 1u : 0u,
+                           (const int *)(D->ws + res.exp_off), rb, rs, (uint32_t)cnt,
+                           P->net.prefactor, partials, first ? 1 : 0,
+                           s_lo + S >= hi ? D->host_partials_dev : (qtn_partial *)nullptr,
+                           (SCALE && D->L.exp_bytes) ? (uint32_t *)(D->ws + D->L.data_bytes) : (uint32_t *)nullptr,
+                           D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
+                           SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0,
+                           folded ? (const double2 *)(D->ws + D->L.dot_off) : (const double2 *)nullptr,
+                           (uint64_t)D->L.dot_slots, dot_gx);
+        first = false;
+      } else {
+        const size_t g = (size_t)(u - 1);
+        const LaunchGroup &G = X.launches[g];
+        if (G.kind == 0) {
+          const bool timed = D->timing;
+          double tb = 0, tf = 0;
+          if (timed) {
+            if (D->ev_used + 2 > D->ev.size()) {
+              for (int j = 0; j < 64; ++j) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                D->ev.push_back(e);
+              }
+            }
+            HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
+          }
+          // at most kMaxGroupProgs programs per launch
+          for (size_t p0 = 0; p0 < G.programs.size(); p0 += kMaxGroupProgs) {
+            GroupArgs ga;
+            std::memset(&ga, 0, sizeof(ga));
+            uint64_t total = 0;
+            for (size_t k = p0; k < G.programs.size() && k < p0 + kMaxGroupProgs; ++k) {
+              const Program &pr = X.programs[G.programs[k]];
+              const uint32_t j = ga.nprog++;
+              const uint64_t items = (pr.bdep ? B : 1) * (pr.sdep ? cnt : 1);
+              total += items;
+              tb += (double)items * D->prog_bytes[G.programs[k]];
+              tf += (double)items * D->prog_flops[G.programs[k]];
+              ga.item_end[j] = (uint32_t)total;
+              ga.nsteps[j] = (uint16_t)pr.steps.size();
+              ga.nstage[j] = (uint16_t)(pr.staged.size() + pr.staged_global.size());
+              ga.bdep[j] = pr.bdep ? 1 : 0;
+              ga.sdep[j] = pr.sdep ? 1 : 0;
+              ga.ns[j] = (uint32_t)cnt;
+              ga.blob[j] = D->blobbuf + D->blob_off[G.programs[k]];
+              ga.scratch[j] = D->ws + D->L.scratch_off;
+              ga.scratch_stride[j] = scratch_stride;
+              ga.s_lo[j] = s_lo;
+            }
+            const uint64_t cap = D->mode == MODE_SLICE ? D->L.wg_slots : 2048;
+            const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
+            hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), D->lds_total,
+                               stream, ga, (uint32_t)total, D->lds_bytes, D->max_slots, D->desc_bytes);
+          }
+          if (timed) {
+            HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
+            D->ev_used += 2;
+            D->ev_bytes.push_back(tb);
+            D->ev_flops.push_back(tf);
+            D->ev_step.push_back(-1);
+          }
+        } else {
+          const int st = G.step;
+          const uint32_t nb = sch.steps[st].bdep ? (uint32_t)B : 1;
+          const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
+          const uint64_t Q = (uint64_t)nb * ns;
+          const PStep &d0 = D->steps[st];
+          const bool streaming = d0.rC >= kStreamMinRank && d0.nk <= 4 && d0.nvary >= 1 && d0.nvary <= 4;
+          const bool timed = D->timing && streaming;
+          if (timed) {
+            if (D->ev_used + 2 > D->ev.size()) {
+              for (int j = 0; j < 64; ++j) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                D->ev.push_back(e);
+              }
+            }
+            HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
+          }
+          const StepTune tu = D->tune.empty() ? StepTune() : D->tune[st];
+          if (int rc = launch_grid_step<SCALE>(P, D, st, stream, s_lo, cnt, tu, &dot_gx)) return rc;
+          if (timed) {
+            HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
+            D->ev_used += 2;
+            D->ev_bytes.push_back((double)Q * D->step_bytes[st]);
+            D->ev_flops.push_back((double)Q * D->step_flops[st]);
+            D->ev_step.push_back(st);
+          }
+        }
+      }
+      return QTN_OK;
+    };
+    if (levels) {
+      std::vector<int> grp;
+      for (int lv = 0; lv < lg.nlevels; ++lv) {
+        grp.clear();
+        for (int u = 1; u + 1 < U; ++u) {
+          if (lg.level[u] != lv) continue;
+          const LaunchGroup &G = X.launches[(size_t)(u - 1)];
+          const StepTune tu = (G.kind == 1 && !D->tune.empty()) ? D->tune[G.step] : StepTune();
+          if (G.kind == 1 && multi_shape(D->steps[G.step], SCALE, tu.stream_only) >= 0)
+            grp.push_back(u);
+          else if (int rc = launch_unit(u, stream))
+            return rc;
+        }
+        for (size_t i = 0; i < grp.size(); i += kMaxMulti) {
+          const size_t n = std::min<size_t>(grp.size() - i, kMaxMulti);
+          if (n == 1) {
+            if (int rc = launch_unit(grp[i], stream)) return rc;
+          } else if (int rc = launch_multi<SCALE>(P, D, &grp[i], n, stream, s_lo, cnt)) {
+            return rc;
+          }
+        }
+      }
+      if (int rc = launch_unit(U - 1, stream)) return rc;   // the slice sum
+      continue;
+    }
     if (multi) {
       // side streams start after everything before this wave
       HIP_TRY(hipEventRecord(D->fork_ev, stream));
       for (int k = 0; k + 1 < lg.nstreams; ++k) HIP_TRY(hipStreamWaitEvent(D->side[k], D->fork_ev, 0));
     }
-    const int U = (int)lg.deps.size();
     for (int ui = 0; ui < U; ++ui) {
       // timing keeps the schedule order on one stream
       const int u = multi ? lg.order[ui] : ui;
@@ -2012,104 +2352,7 @@ static int run_waves(qtn_plan_t *P, DeviceState *D, uint64_t lo, uint64_t hi, hi
       if (multi)
         for (int d : lg.deps[u])
           if (lg.stream[d] != lg.stream[u]) HIP_TRY(hipStreamWaitEvent(ustream, D->unit_ev[d], 0));
-      {
-        const hipStream_t stream = ustream;
-        if (u == 0) {
-          // exponents were cleared at bind time or by the previous slice sum
-        } else if (u == U - 1) {
-          const uint64_t rb = res.bdep ? (res.sdep ? S : 1) : 0, rs = res.sdep ? 1 : 0;
-          hipLaunchKernelGGL((slice_sum<SCALE>), dim3((unsigned)B), dim3(256), 0, stream,
-                             (const void *)(D->ws + res.data_off), res.f64 ? 1u : 0u,
-                             (const int *)(D->ws + res.exp_off), rb, rs, (uint32_t)cnt,
-                             P->net.prefactor, partials, first ? 1 : 0,
-                             s_lo + S >= hi ? D->host_partials_dev : (qtn_partial *)nullptr,
-                             (SCALE && D->L.exp_bytes) ? (uint32_t *)(D->ws + D->L.data_bytes) : (uint32_t *)nullptr,
-                             D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
-                             SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0,
-                             folded ? (const double2 *)(D->ws + D->L.dot_off) : (const double2 *)nullptr,
-                             (uint64_t)D->L.dot_slots, dot_gx);
-          first = false;
-        } else {
-          const size_t g = (size_t)(u - 1);
-          const LaunchGroup &G = X.launches[g];
-          if (G.kind == 0) {
-            const bool timed = D->timing;
-            double tb = 0, tf = 0;
-            if (timed) {
-              if (D->ev_used + 2 > D->ev.size()) {
-                for (int j = 0; j < 64; ++j) {
-                  hipEvent_t e;
-                  HIP_TRY(hipEventCreate(&e));
-                  D->ev.push_back(e);
-                }
-              }
-              HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
-            }
-            // at most kMaxGroupProgs programs per launch
-            for (size_t p0 = 0; p0 < G.programs.size(); p0 += kMaxGroupProgs) {
-              GroupArgs ga;
-              std::memset(&ga, 0, sizeof(ga));
-              uint64_t total = 0;
-              for (size_t k = p0; k < G.programs.size() && k < p0 + kMaxGroupProgs; ++k) {
-                const Program &pr = X.programs[G.programs[k]];
-                const uint32_t j = ga.nprog++;
-                const uint64_t items = (pr.bdep ? B : 1) * (pr.sdep ? cnt : 1);
-                total += items;
-                tb += (double)items * D->prog_bytes[G.programs[k]];
-                tf += (double)items * D->prog_flops[G.programs[k]];
-                ga.item_end[j] = (uint32_t)total;
-                ga.nsteps[j] = (uint16_t)pr.steps.size();
-                ga.nstage[j] = (uint16_t)(pr.staged.size() + pr.staged_global.size());
-                ga.bdep[j] = pr.bdep ? 1 : 0;
-                ga.sdep[j] = pr.sdep ? 1 : 0;
-                ga.ns[j] = (uint32_t)cnt;
-                ga.blob[j] = D->blobbuf + D->blob_off[G.programs[k]];
-                ga.scratch[j] = D->ws + D->L.scratch_off;
-                ga.scratch_stride[j] = scratch_stride;
-                ga.s_lo[j] = s_lo;
-              }
-              const uint64_t cap = D->mode == MODE_SLICE ? D->L.wg_slots : 2048;
-              const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
-              hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), D->lds_total,
-                                 stream, ga, (uint32_t)total, D->lds_bytes, D->max_slots, D->desc_bytes);
-            }
-            if (timed) {
-              HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
-              D->ev_used += 2;
-              D->ev_bytes.push_back(tb);
-              D->ev_flops.push_back(tf);
-              D->ev_step.push_back(-1);
-            }
-          } else {
-            const int st = G.step;
-            const uint32_t nb = sch.steps[st].bdep ? (uint32_t)B : 1;
-            const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
-            const uint64_t Q = (uint64_t)nb * ns;
-            const PStep &d0 = D->steps[st];
-            const bool streaming = d0.rC >= kStreamMinRank && d0.nk <= 4 && d0.nvary >= 1 && d0.nvary <= 4;
-            const bool timed = D->timing && streaming;
-            if (timed) {
-              if (D->ev_used + 2 > D->ev.size()) {
-                for (int j = 0; j < 64; ++j) {
-                  hipEvent_t e;
-                  HIP_TRY(hipEventCreate(&e));
-                  D->ev.push_back(e);
-                }
-              }
-              HIP_TRY(hipEventRecord(D->ev[D->ev_used], stream));
-            }
-            const StepTune tu = D->tune.empty() ? StepTune() : D->tune[st];
-            if (int rc = launch_grid_step<SCALE>(P, D, st, stream, s_lo, cnt, tu, &dot_gx)) return rc;
-            if (timed) {
-              HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
-              D->ev_used += 2;
-              D->ev_bytes.push_back((double)Q * D->step_bytes[st]);
-              D->ev_flops.push_back((double)Q * D->step_flops[st]);
-              D->ev_step.push_back(st);
-            }
-          }
-        }
-      }
+      if (int rc = launch_unit(u, ustream)) return rc;
       if (multi && lg.record[u]) HIP_TRY(hipEventRecord(D->unit_ev[u], ustream));
     }
     if (multi) {
