@@ -86,9 +86,33 @@ def _oracle_worker(args):
     return val, time.perf_counter() - t
 
 
-def cpu_baseline(inst, cut, order, budget_s=20.0):
-    """Times the oracle on a bounded sample of the same workload."""
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_workers(max_rank: int) -> int:
+    """Worker processes for the oracle: the host cores (at most 16, the CPU
+    share of one GPU), and no more than 70% of the RAM holds at three
+    complex128 tensors of the largest rank per worker."""
     cores = max(1, min(16, os.cpu_count() or 1))
+    try:
+        ram = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES")
+        cores = max(1, min(cores, int(0.7 * ram // (3 * 16 * (1 << max(0, max_rank))))))
+    except (ValueError, OSError):
+        pass
+    return cores
+
+
+def cpu_baseline(inst, cut, order, max_rank, budget_s=20.0):
+    """Times the oracle on a bounded sample of the same workload."""
+    cores = oracle_workers(max_rank)
     k = len(cut)
     # one probe to size the sample
     slices_per_job = 1 if k else 0
@@ -118,7 +142,7 @@ def cpu_baseline(inst, cut, order, budget_s=20.0):
         unit = "amplitudes/s"
         amps = value
     return {"value": value, "unit": unit, "amplitudes_per_sec": amps, "cores": cores,
-            "kind": "oracle", "sample": "%d %s of the workload (bitstrings cycled), complex128 "
+            "cpu_model": host_cpu_model(), "kind": "oracle", "sample": "%d %s of the workload (bitstrings cycled), complex128 "
             "variable elimination with the plan's order and cut, %d worker processes" %
             (jobs, "slices" if k else "uncut amplitudes", cores),
             "cpu_seconds": sum(r[1] for r in res), "wall_seconds": wall}, vals
@@ -194,7 +218,7 @@ def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
         plan.close()
     out["mixed_over_fp64"] = out["mixed"]["slices_per_sec"] / out["fp64"]["slices_per_sec"]
     if with_cpu:
-        cores = max(1, min(16, os.cpu_count() or 1))
+        cores = oracle_workers(int(info["width"]))
         order = plan_instance(inst, cut_vars=cut).order()
         nsub = max(sub, min(nsl, 4 * cores))
         work, owner = [], []
@@ -225,7 +249,7 @@ def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
         out["subset"] = {"slices": sub, "max_rel_err_mixed_vs_oracle": max(errs["mixed"]),
                          "max_rel_err_fp64_vs_oracle": max(errs["fp64"]), "max_kappa": max(kappa)}
         out["cpu_baseline"] = {"value": B * nsub / wall, "unit": "slices/s", "cores": cores,
-                               "kind": "oracle",
+                               "cpu_model": host_cpu_model(), "kind": "oracle",
                                "sample": "slices [0, %d) of all %d bitstrings, complex128 variable "
                                          "elimination with the plan's cut and order, %d worker "
                                          "processes" % (nsub, B, cores),
@@ -410,7 +434,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         order = mixed.order()
-        cb, vals = cpu_baseline(inst, cut, order)
+        cb, vals = cpu_baseline(inst, cut, order, int(info["width"]))
         line["cpu_baseline"] = cb
         if k == 0:
             errs = []

@@ -107,9 +107,12 @@ typedef struct {
   int32_t width;             /* largest rank of a slice tensor the schedule materialises  */
   int32_t n_steps;           /* contraction steps per slice                               */
   int32_t n_tensors;
-  double log2_flops;         /* real flops per slice-contraction (all bitstrings)          */
-  double bytes_per_slice;    /* algorithmic HBM bytes per slice (all bitstrings)          */
-  double flops_hoisted;      /* flops of slice-invariant steps, once per wave             */
+  double log2_flops;         /* real flops per slice-contraction (all bitstrings), the
+                                slice-invariant steps' share amortised over the 2^k slices */
+  double bytes_per_slice;    /* algorithmic HBM bytes per slice (all bitstrings), same   */
+  double flops_hoisted;      /* flops of the slice-invariant steps; qtn_contract runs them
+                                once per wave of slices, so a range of w waves executes
+                                w * flops_hoisted beyond the per-slice work              */
   double work;               /* sum over buckets of 2^(|N+(v)|+1), one slice, one bitstring */
   double prefactor;          /* 2^{-n/2} times the factor normalisations                 */
   double search_seconds;     /* time spent in the cut search                              */

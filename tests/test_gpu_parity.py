@@ -75,6 +75,33 @@ def test_closed_form_gamma0(precision):
         assert _rel(a, ref, 20) <= TOL[precision]
 
 
+@pytest.mark.parametrize("which", ["gamma0", "beta0", "betapi2"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_closed_forms_with_64bit_storage(precision, which):
+    """The three closed forms of the circuit (gamma = 0; beta = 0: RX = I;
+    beta = pi/2: RX(pi) = -iX commutes with the phases) on a 30-qubit,
+    depth-2 instance whose mixed-form plan stores its grid-step tensors in
+    the 64-bit form, so the FP32 leg exercises that storage."""
+    print("case closed form", which, precision, flush=True)
+    n, p = 30, 2
+    inst = make_instance(n, p, 4, 7)
+    gamma, beta = list(inst.gamma), list(inst.beta)
+    if which == "gamma0":
+        gamma = [0.0] * p
+    elif which == "beta0":
+        beta = [0.0] * p
+    else:
+        beta = [math.pi / 2] * p
+    plan = qtn.qtn_plan(n, inst.edges, p, gamma, beta, inst.bitstrings, k=2, precision=precision)
+    plan.bind_torch(4)
+    if precision == "fp32":
+        steps, tens = plan.export()
+        assert any(t[1] == 1 and not (t[2] & 4) for t in tens), "no 64-bit tensors"
+    for b, a in enumerate(_amps(plan, 0, 4)):
+        ref = Q.closed_form_amplitude(n, inst.edges, p, gamma, beta, inst.bitstrings[b])
+        assert _rel(a, ref, n) <= TOL[precision], (b, a, ref)
+
+
 @pytest.mark.parametrize("mode", ["wide", "slice"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_n40_p2_b32_k8_all_amplitudes(precision, mode):
