@@ -1147,6 +1147,27 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
     soff[v] = bytes;
     bytes += (1u << (nkv[v] + nlo[v])) * 16u;   // staged as complex128
   }
+  // row bits each operand depends on, and the visiting order of the four
+  // low row bits: bits that large operands lack innermost, so that their
+  // staged runs serve consecutive rows (weights: run elements saved)
+  uint32_t rdep[NV];
+  uint32_t wbit[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    rdep[v] = (d.in[v].mask & cb) >> 8;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (!((rdep[v] >> b) & 1u)) wbit[b] += 1u << (nkv[v] + nlo[v]);
+  }
+  uint32_t rord = 0;   // 2 bits per position: the row bit visited there
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    // position of bit i: the number of heavier bits (ties: lower bit first)
+    uint32_t rank = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rank += (wbit[b] > wbit[i] || (wbit[b] == wbit[i] && b < i)) ? 1u : 0u;
+    rord |= (uint32_t)i << (2u * rank);
+  }
   constexpr int fold = FOLD ? 0 : -1;
   const uint64_t Q = (uint64_t)nb * ns;
   const uint32_t rows = (1u << d.rC) >> 8;
@@ -1210,10 +1231,18 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
       // operand bases of the current chunk of 16 rows: instance offset plus
       // the index part of the row bits above the lowest four
       const char *cbase[NV];
+      uint32_t key[NV];
 #pragma unroll 1
       for (uint32_t jj = 0; jj < jspan; ++jj) {
-        const uint32_t row = u * jspan + jj;
-        if (jj == 0 || (row & 15u) == 0) {
+        // rows of a 16-row chunk in the order rord (innermost bits first)
+        const uint32_t lo4 = jj & 15u;
+        const uint32_t row = u * jspan + (jspan >= 16u
+                                             ? (jj & ~15u) | (((lo4 >> 0) & 1u) << (rord & 3u)) |
+                                                   (((lo4 >> 1) & 1u) << ((rord >> 2) & 3u)) |
+                                                   (((lo4 >> 2) & 1u) << ((rord >> 4) & 3u)) |
+                                                   (((lo4 >> 3) & 1u) << ((rord >> 6) & 3u))
+                                             : jj);
+        if (jj == 0 || lo4 == 0) {
 #pragma unroll
           for (int v = 0; v < NV; ++v)
             cbase[v] = (const char *)d.in[v].base +
@@ -1222,6 +1251,11 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
         __syncthreads();  // the previous row's readers are done
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+          // the staged runs of v depend only on its row bits: when those are
+          // the previous row's, the runs in LDS are this row's too
+          const uint32_t kv = row & rdep[v];
+          if (jj > 0 && kv == key[v]) continue;
+          key[v] = kv;
           constexpr uint32_t esz_f = 8u, esz_d = 16u;
           const uint32_t esz = v < NF ? esz_f : esz_d;
           // the table entry is the same for every lane
@@ -1281,7 +1315,7 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
             acc.x = ldexp(acc.x, -sh);
             acc.y = ldexp(acc.y, -sh);
           }
-          dot_add(DA, dsv, DS, dsw[jj], row, acc);
+          dot_add(DA, dsv, DS, dsw[row - u * jspan], row, acc);
         } else if (SCALE) {
           wmax = max(wmax, store_scaled(op, of, ((uint64_t)row << 8) | t, acc, sh));
         } else {
