@@ -50,7 +50,8 @@ def kernel_sources_sha256() -> str:
 
 def kernel_file_tag(kernel: str) -> str:
     """File-name form of a kernel instance name, e.g. step_tiled_true_4_3_3."""
-    return "".join(c if c.isalnum() else "_" for c in kernel).replace("__", "_").strip("_")
+    import re
+    return re.sub("_+", "_", "".join(c if c.isalnum() else "_" for c in kernel)).strip("_")
 
 
 def measured_traffic(workload: str, kernel: str):
