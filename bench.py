@@ -196,7 +196,10 @@ def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
         el = time.perf_counter() - t
         res[tag] = [p.value() for p in plan.contract(0, sub, stream)]
         out[tag] = {"slices_per_sec": B * nsl * reps / el, "amplitudes_per_sec": B * reps / el,
-                    "ms_per_step": 1e3 * el / reps}
+                    "ms_per_step": 1e3 * el / reps,
+                    # 1: some intermediate in the 64-bit form, rescaling kernels;
+                    # 0: every tensor complex128, the FP64 kernels
+                    "rescaled": int(plan.info()["rescaled"])}
         print("# %s %s: %.1f ms per contraction of %d slice instances" %
               (name, tag, 1e3 * el / reps, B * nsl), file=sys.stderr, flush=True)
         if tag == "mixed":
@@ -418,6 +421,7 @@ def main():
         "config": {"workload": args.workload, "n": inst.n, "p": inst.p, "bitstrings": B,
                    "k": k, "slices_per_amplitude": nsl, "max_slice_rank": info["width"],
                    "seed": args.seed, "slices_per_wave": S, "graph": "random 3-regular",
+                   "rescaled": int(info["rescaled"]),
                    "precision": "mixed: large tensors stored in 8 bytes (shared 8-bit exponent, "
                                 "two 28-bit mantissas) with per-instance power-of-two rescaling, "
                                 "fp64 arithmetic, fp64 compensated slice sum"},

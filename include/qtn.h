@@ -124,6 +124,11 @@ typedef struct {
   double slice_scratch_bytes;/* global scratch per workgroup, same mode                   */
   int32_t mf_width;          /* width of the min-fill order on G - C, Sec. II B (largest bag
                                 minus one; the cut search's fitness); width <= mf_width + 1 */
+  int32_t rescaled;          /* bit 0 (grid-wide mode), bit 1 (one-workgroup-per-instance
+                                mode): the mixed form keeps some intermediate in the 64-bit
+                                form outside LDS and runs the rescaling kernels; when clear,
+                                every stored tensor is complex128 and the FP64 kernels run
+                                (always for FP64 plans)                                   */
 } qtn_plan_info;
 
 /* Fills defaults: k = -1, max_rank = 0, k_max = 24, cut_vars = NULL, seed = 0,

@@ -175,6 +175,15 @@ static int plan_rest(qtn_plan_t *P, const qtn_plan_opts &opts, const qtn_graph *
     P->exec_mode = opts.exec_mode;
     P->exec[MODE_WIDE] = build_exec(P->sched, MODE_WIDE, kLdsBudget);
     P->exec[MODE_SLICE] = build_exec(P->sched, MODE_SLICE, kLdsBudget);
+    for (int m = 0; m < 2; ++m) {
+      P->scaled[m] = false;
+      if (P->precision == QTN_FP64) continue;
+      for (size_t t = 0; t < P->sched.tensors.size(); ++t) {
+        const Tensor &T = P->sched.tensors[t];
+        const int loc = P->exec[m].loc[t];
+        if (!T.leaf && !T.f64 && (loc == LOC_GLOBAL || loc == LOC_SCRATCH)) P->scaled[m] = true;
+      }
+    }
     if (const char *e = std::getenv("QTN_PLAN_REPORT"); e && e[0] == '1') {
       // launch structure of both execution modes, for tuning
       for (int m = 0; m < 2; ++m) {
@@ -360,6 +369,7 @@ extern "C" int qtn_plan_query(const qtn_plan_t *P, qtn_plan_info *info) {
   info->slice_lds_bytes = P->exec[MODE_SLICE].lds_bytes;
   info->slice_scratch_bytes = (double)P->exec[MODE_SLICE].scratch_per_wg;
   info->mf_width = P->mf_width;
+  info->rescaled = (P->scaled[MODE_WIDE] ? 1 : 0) | (P->scaled[MODE_SLICE] ? 2 : 0);
   return QTN_OK;
 }
 

@@ -33,6 +33,11 @@ struct qtn_plan_s {
   uint64_t work = 0;       // sum 2^(|N+(v)|+1)
   double search_seconds = 0.0;
   int f64_below_rank = 0;  // intermediates of smaller rank are stored as complex128
+  // per execution mode: the rescaling kernels run, i.e. the mixed form keeps
+  // at least one intermediate in the 64-bit form outside LDS (values kept in
+  // range for its 8-bit exponent); with every stored tensor complex128 (LDS
+  // holds complex128 anyway) the FP64 kernels compute the same thing
+  bool scaled[2] = {false, false};
   int exec_mode = -1;      // -1 chosen per binding, else qtn::ExecMode
   qtn::ExecPlan exec[2];   // MODE_WIDE, MODE_SLICE
   qtn::DeviceState *dev = nullptr;

@@ -1724,6 +1724,8 @@ static void fill_tables(qtn_plan_t *P, DeviceState *D, const ExecPlan &X, std::v
   const Schedule &sch = P->sched;
   const uint64_t S = D->L.S;
   const uint64_t B = P->net.B;
+  // exponent words exist for every mixed-form plan (a plan whose tensors are
+  // all complex128 runs the rescaling kernels when batched with one that is not)
   const bool scaled = P->precision != QTN_FP64;
   // algorithmic bytes and flops of each step, per instance
   D->step_bytes.assign(sch.steps.size(), 0.0);
@@ -2448,7 +2450,7 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
     }
   }
   auto enqueue = [&](hipStream_t st, bool concurrent) {
-    return P->precision == QTN_FP64 ? run_waves<false>(P, D, lo, hi, st, concurrent)
+    return !P->scaled[D->mode] ? run_waves<false>(P, D, lo, hi, st, concurrent)
                                     : run_waves<true>(P, D, lo, hi, st, concurrent);
   };
   if (D->use_graphs) {
@@ -2697,7 +2699,7 @@ extern "C" int qtn_plan_autotune(qtn_plan_t *P, void *stream_v, const char *cach
   }
   std::memset(stats, 0, sizeof(*stats));
   const hipStream_t stream = (hipStream_t)stream_v;
-  return P->precision == QTN_FP64 ? autotune_impl<false>(P, stream, cache_path, stats)
+  return !P->scaled[P->dev->mode] ? autotune_impl<false>(P, stream, cache_path, stats)
                                   : autotune_impl<true>(P, stream, cache_path, stats);
 }
 
@@ -2788,6 +2790,10 @@ extern "C" int qtn_batch_contract(qtn_plan_t *const *plans, uint32_t n_plans, co
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   const int prec = plans[0] ? plans[0]->precision : 0;
+  // one kernel form for the launch: the rescaling one if any plan needs it
+  // (a mixed-form plan whose tensors are all complex128 runs it correctly)
+  bool scaled0 = false;
+  for (uint32_t i = 0; i < n_plans; ++i) scaled0 = scaled0 || (plans[i] && plans[i]->scaled[MODE_SLICE]);
   uint64_t total = 0;
   for (uint32_t i = 0; i < n_plans; ++i) {
     qtn_plan_t *P = plans[i];
@@ -2824,7 +2830,7 @@ extern "C" int qtn_batch_contract(qtn_plan_t *const *plans, uint32_t n_plans, co
     total += P->net.B;
   }
   hipStream_t stream = (hipStream_t)stream_v;
-  const int rc = prec == QTN_FP64 ? batch_enqueue<false>(plans, n_plans, slice_lo, slice_hi, stream)
+  const int rc = !scaled0 ? batch_enqueue<false>(plans, n_plans, slice_lo, slice_hi, stream)
                                   : batch_enqueue<true>(plans, n_plans, slice_lo, slice_hi, stream);
   if (rc) return rc;
   if (int w = wait_stream(stream, "qtn_batch_contract")) return w;
@@ -2978,7 +2984,7 @@ extern "C" int qtn_contract_noalloc(qtn_plan_t *P, uint64_t lo, uint64_t hi, uin
   if (!N->blob.empty())
     HIP_TRY(hipMemcpyAsync(base + N->blob_off, N->blob.data(), N->blob.size(), hipMemcpyHostToDevice, stream));
   D.blobbuf = base + N->blob_off;
-  const bool scaled = P->precision != QTN_FP64;
+  const bool scaled = P->scaled[D.mode];
   if (scaled && D.L.exp_bytes) {
     const uint64_t words = D.L.exp_bytes / 4;
     const unsigned blocks = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((words + 255) / 256, 1024));
@@ -3069,7 +3075,7 @@ extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *nam
   for (const LaunchGroup &G : X.launches)
     if (G.kind == 1 && G.step == step) {
       const PStep &d = D->steps[step];
-      const bool sc = P->precision != QTN_FP64;
+      const bool sc = P->scaled[D->mode];
       const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
       const std::string tf = sc ? "true" : "false";
       if (!streaming)

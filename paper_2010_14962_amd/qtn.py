@@ -53,7 +53,8 @@ class QtnPlanInfo(ctypes.Structure):
                 ("search_seconds", c_double), ("precision", c_int32),
                 ("f64_below_rank", c_int32), ("n_programs_wide", c_int32),
                 ("n_launches_wide", c_int32), ("slice_lds_bytes", c_uint32),
-                ("slice_scratch_bytes", c_double), ("mf_width", c_int32)]
+                ("slice_scratch_bytes", c_double), ("mf_width", c_int32),
+                ("rescaled", c_int32)]
 
 
 class QtnKernelTiming(ctypes.Structure):

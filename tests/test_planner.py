@@ -209,3 +209,19 @@ def test_workspace_layout_self_check(name, k, mode, precision):
     P = plan_instance(inst, k=k, max_rank=26, precision=precision, exec_mode=mode)
     for S in (1, 3, 64, 1 << min(P.info()["k"], 10)):
         assert P.workspace_bytes(S) > 0
+
+
+def test_rescaling_only_with_64bit_tensors():
+    """The mixed form runs the rescaling kernels only when some intermediate
+    is stored in the 64-bit form outside LDS; with every stored tensor
+    complex128 it reduces to the FP64 kernels.  FP64 plans never rescale."""
+    big = workload_instance("qaoa_n120_p1_b8")
+    P = plan_instance(big, k=-1, max_rank=26, precision="fp32")
+    steps, tens = P.export()
+    assert any(t[1] == 1 and not (t[2] & 4) for t in tens)
+    assert P.info()["rescaled"] & 1
+    assert plan_instance(big, k=-1, max_rank=26, precision="fp64").info()["rescaled"] == 0
+    # width 8: every intermediate of a slice lives in LDS (complex128 there)
+    small = workload_instance("qaoa_n120_p1_b8_k16")
+    Ps = plan_instance(small, k=16, max_rank=26, precision="fp32")
+    assert Ps.info()["rescaled"] == 0
