@@ -1350,13 +1350,14 @@ __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, ui
 // microseconds.  Here each member owns a contiguous range of the launch's
 // blocks and runs as its own kernel would, with its block coordinates
 // taken from that range.  The member kernels are the common shapes of the
-// mid-size steps (1 or 2 summed variables, 2 or 3 varying operands, at most
-// one of them in the 64-bit form); other steps launch on their own.
+// mid-size steps (LDS-staged: 1 or 2 summed variables and 2 or 3 varying
+// operands; direct: 1 summed variable and 2 varying operands; at most one
+// operand in the 64-bit form); other steps launch on their own.
 constexpr int kMaxMulti = 4;
 struct MultiArgs {
   PStep step[kMaxMulti];
   uint32_t n;
-  uint32_t vid[kMaxMulti];       // member shape (multi_variant)
+  uint32_t vid[kMaxMulti];       // member shape (multi_shape)
   uint32_t blk_end[kMaxMulti];   // cumulative block counts
   uint32_t gx[kMaxMulti];        // the member's x extent (y = blocks / gx)
   uint32_t nb[kMaxMulti], ns[kMaxMulti], jspan[kMaxMulti];
