@@ -514,6 +514,21 @@ struct WgCtx {
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// pext of the low 8 bits of x under an 8-bit mask m that is the same in
+// every lane, unrolled over the 8 mask bits: no loop and no branch (the bit
+// loop of dpext costs a scalar branch and a few scalar instructions per set
+// bit, and every wave of the workgroup runs it for every operand and step)
+__device__ __forceinline__ uint32_t pext8_uniform(uint32_t x, uint32_t m) {
+  uint32_t r = 0, k = 0;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint32_t mb = (m >> b) & 1u;
+    r |= ((x >> b) & mb) << k;
+    k += mb;
+  }
+  return r;
+}
+
 // One step of a workgroup program.  Complex128 tensors in LDS are not
 // rescaled: they carry their power-of-two exponent in sE[slot] and FP64 has
 // range to spare.  Outputs stored in global memory or scratch keep the
@@ -544,7 +559,7 @@ __device__ void wg_step_n(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint
     const uint32_t m = used ? uni(mk[i]) : 0u;
     mk[i] = m;
     mt[i] = uni(mt[i]);
-    lo[i] = dpext(t & 255u, m & 255u);
+    lo[i] = pext8_uniform(t, m & 255u);
     hm[i] = m >> 8;
     hs[i] = __popc(m & 255u);
     loff[i] = used ? uni(ok[i]) / 16 : 0u;
@@ -559,6 +574,7 @@ __device__ void wg_step_n(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint
     gptr[i] = nullptr;
     gf64[i] = 1;
     if (i >= nin) continue;
+    if (LDSONLY && !SCALE) continue;   // nothing outside LDS, no exponents
     const uint32_t loc = (mt[i] >> 16) & 255u;
     const int slot = (int16_t)(mt[i] & 0xffffu);
     if (loc == LOC_SCRATCH) {
