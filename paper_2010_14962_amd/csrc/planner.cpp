@@ -515,8 +515,16 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
     for (int t : pool) (has(s.tensors[t], v) ? inputs : keep).push_back(t);
     pool.swap(keep);
     done[v] = 1;
-    // Too many operands: multiply the two smallest first (v stays open).
-    while ((int)inputs.size() > kMaxIn) {
+    std::vector<int> U = union_vars(inputs);
+    std::vector<int> kappa{v};
+    std::vector<int> out;
+    for (int u : U)
+      if (u != v) out.push_back(u);
+    // Too many operands (kMaxIn, or kMaxProgIn for a step that will run in
+    // a workgroup program): multiply the two smallest first (v stays open;
+    // the union, and so the step's index space, does not change).
+    const int limit = (int)out.size() < kSmallRank ? kMaxProgIn : kMaxIn;
+    while ((int)inputs.size() > limit) {
       std::stable_sort(inputs.begin(), inputs.end(), [&](int a, int b) {
         return s.tensors[a].rank() < s.tensors[b].rank();
       });
@@ -525,11 +533,6 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
       inputs.erase(inputs.begin(), inputs.begin() + 2);
       inputs.push_back(pid);
     }
-    std::vector<int> U = union_vars(inputs);
-    std::vector<int> kappa{v};
-    std::vector<int> out;
-    for (int u : U)
-      if (u != v) out.push_back(u);
     // Chain fusion: a following bucket that holds only this result (and a
     // leaf inside it) is summed in the same pass over the same index space.
     if (o.fuse_chains) {
@@ -542,7 +545,8 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
         if (other) break;
         const int lw = leaf_of[w];
         if (lw >= 0) {
-          if ((int)inputs.size() >= kMaxIn) break;
+          const int rC_next = (int)out.size() - 1;
+          if ((int)inputs.size() >= (rC_next < kSmallRank ? kMaxProgIn : kMaxIn)) break;
           bool inside = true;
           for (int u : s.tensors[lw].vars)
             inside &= std::find(out.begin(), out.end(), u) != out.end();
@@ -575,7 +579,7 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
   if (finals.empty()) throw std::runtime_error("empty network");
   while (finals.size() > 1 || s.tensors[finals[0]].leaf) {
     std::vector<int> take(finals.begin(),
-                          finals.begin() + std::min<size_t>(finals.size(), kMaxIn));
+                          finals.begin() + std::min<size_t>(finals.size(), kMaxProgIn));
     std::vector<int> rest(finals.begin() + take.size(), finals.end());
     int cid = emit(take, {}, {});
     rest.insert(rest.begin(), cid);

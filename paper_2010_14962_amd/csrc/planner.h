@@ -13,6 +13,11 @@ namespace qtn {
 using cd = std::complex<double>;
 
 constexpr int kMaxIn = 8;        // inputs of one fused contraction step
+// Inputs of a step small enough for a workgroup program (output rank below
+// kSmallRank): the program kernel holds registers for this many operands
+// (with 8 it needs 130-148 registers, spills, and runs 3 waves per SIMD;
+// with 4, 102 and 4 waves)
+constexpr int kMaxProgIn = 4;
 constexpr int kLeafMaxRank = 12; // largest merged leaf group
 constexpr int kAlwaysF64Rank = 8; // intermediates below this rank stay complex128
 constexpr int kSmallRank = 11;    // steps with fewer output bits run inside one workgroup

@@ -712,7 +712,9 @@ __device__ void wg_step_n(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint
   __syncthreads();
 }
 
-template <bool SCALE>
+// MAXNIN: the largest operand count among the launch's steps (4 or 8); the
+// kernel's registers are those of its largest case.
+template <bool SCALE, int MAXNIN>
 __device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32_t s, const WgCtx &W) {
   const uint32_t nin = uni((uint32_t)st.nin);
   const bool lds_only = (uni((uint32_t)st.wg_flags) & 1u) != 0;
@@ -723,9 +725,16 @@ __device__ void wg_step(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint32
     else                                               \
       wg_step_n<SCALE, N, false>(st, b, sl, s, W);    \
     break;
-  switch (nin) {
-    QTN_WG(1) QTN_WG(2) QTN_WG(3) QTN_WG(4) QTN_WG(5) QTN_WG(6) QTN_WG(7) QTN_WG(8)
-    default: break;
+  if constexpr (MAXNIN <= 4) {
+    switch (nin) {
+      QTN_WG(1) QTN_WG(2) QTN_WG(3) QTN_WG(4)
+      default: break;
+    }
+  } else {
+    switch (nin) {
+      QTN_WG(1) QTN_WG(2) QTN_WG(3) QTN_WG(4) QTN_WG(5) QTN_WG(6) QTN_WG(7) QTN_WG(8)
+      default: break;
+    }
   }
 #undef QTN_WG
 }
@@ -817,7 +826,7 @@ __device__ __forceinline__ void copy_to_lds(QTN_LDS char *dst, const char *__res
 // staging records and first steps into LDS, stages the gate factors, then
 // runs the steps, kDescChunk descriptors at a time.  Items never wait on
 // each other.
-template <bool SCALE>
+template <bool SCALE, int MAXNIN>
 __global__ __launch_bounds__(256) void wg_programs(const GroupArgs ga, uint32_t total, uint32_t lds_bytes,
                                                    int max_slots, uint32_t desc_off) {
   char *smem = wg_smem;
@@ -856,7 +865,7 @@ __global__ __launch_bounds__(256) void wg_programs(const GroupArgs ga, uint32_t 
                     min(nst - k, (uint32_t)kDescChunk) * (uint32_t)sizeof(PStep));
         __syncthreads();
       }
-      wg_step<SCALE>(ps[k % kDescChunk], b, sl, s, W);
+      wg_step<SCALE, MAXNIN>(ps[k % kDescChunk], b, sl, s, W);
     }
   }
 }
@@ -1725,12 +1734,36 @@ static std::vector<double> leaf_host(const qtn_plan_t *P, std::vector<uint64_t> 
 
 static int set_program_lds(uint32_t lds_total) {
   if (lds_total > 64 * 1024) {
-    HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<true>,
+    HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<true, 4>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
-    HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<false>,
+    HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<false, 4>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
+    HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<true, 8>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
+    HIP_TRY(hipFuncSetAttribute((const void *)wg_programs<false, 8>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_total));
   }
   return QTN_OK;
+}
+
+// Largest operand count among the steps of some programs: the program kernel
+// with registers for 4 operands runs them when it is at most 4.
+static int programs_max_nin(const Schedule &sch, const ExecPlan &X, const int *progs, size_t n) {
+  size_t m = 0;
+  for (size_t k = 0; k < n; ++k)
+    for (int st : X.programs[progs[k]].steps) m = std::max(m, sch.steps[st].in.size());
+  return (int)m;
+}
+
+template <bool SCALE>
+static void launch_programs(int max_nin, dim3 grid, uint32_t lds_total, hipStream_t stream, const GroupArgs &ga,
+                            uint32_t total, uint32_t lds_bytes, int max_slots, uint32_t desc_off) {
+  if (max_nin <= 4)
+    hipLaunchKernelGGL((wg_programs<SCALE, 4>), grid, dim3(256), lds_total, stream, ga, total, lds_bytes,
+                       max_slots, desc_off);
+  else
+    hipLaunchKernelGGL((wg_programs<SCALE, 8>), grid, dim3(256), lds_total, stream, ga, total, lds_bytes,
+                       max_slots, desc_off);
 }
 
 static void fill_tables(qtn_plan_t *P, DeviceState *D, const ExecPlan &X, std::vector<char> &blob);
@@ -2327,8 +2360,10 @@ static int run_waves(qtn_plan_t *P, DeviceState *D, uint64_t lo, uint64_t hi, hi
             }
             const uint64_t cap = D->mode == MODE_SLICE ? D->L.wg_slots : 2048;
             const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
-            hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), D->lds_total,
-                               stream, ga, (uint32_t)total, D->lds_bytes, D->max_slots, D->desc_bytes);
+            const size_t np = std::min<size_t>(G.programs.size() - p0, (size_t)kMaxGroupProgs);
+            launch_programs<SCALE>(programs_max_nin(sch, X, G.programs.data() + p0, np), dim3((unsigned)grid),
+                                   D->lds_total, stream, ga, (uint32_t)total, D->lds_bytes, D->max_slots,
+                                   D->desc_bytes);
           }
           if (timed) {
             HIP_TRY(hipEventRecord(D->ev[D->ev_used + 1], stream));
@@ -2768,8 +2803,14 @@ static int batch_enqueue(qtn_plan_t *const *plans, uint32_t n, const uint64_t *l
     }
     if (int rc = set_program_lds(lds_total)) return rc;
     const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>(total, cap));
-    hipLaunchKernelGGL((wg_programs<SCALE>), dim3((unsigned)grid), dim3(256), lds_total, stream, ga,
-                       (uint32_t)total, lds_bytes, max_slots, desc_off);
+    int max_nin = 0;
+    for (uint32_t i = 0; i < n; ++i)
+      if (lo[i] != hi[i]) {
+        const int zero = 0;
+        max_nin = std::max(max_nin, programs_max_nin(plans[i]->sched, plans[i]->exec[MODE_SLICE], &zero, 1));
+      }
+    launch_programs<SCALE>(max_nin, dim3((unsigned)grid), lds_total, stream, ga, (uint32_t)total, lds_bytes,
+                           max_slots, desc_off);
   }
   for (uint32_t i = 0; i < n; ++i) {
     qtn_plan_t *P = plans[i];
