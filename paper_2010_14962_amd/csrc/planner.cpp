@@ -533,25 +533,41 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
       inputs.erase(inputs.begin(), inputs.begin() + 2);
       inputs.push_back(pid);
     }
-    // Chain fusion: a following bucket that holds only this result (and a
-    // leaf inside it) is summed in the same pass over the same index space.
+    // Chain fusion: a following bucket that holds this result, a leaf and
+    // other tensors whose variables all lie in this step's outputs is summed
+    // in the same pass over the same index space (the index space does not
+    // grow; the intermediate of the first bucket is never stored).  Without
+    // the other tensors this is the plain chain of one result and its leaf;
+    // with them it also removes an expansion followed by a contraction, as
+    // at the end of the n = 80, depth-2 orders (QTN_ABSORB=0 keeps the plain
+    // chains only).
+    static const bool absorb = [] {
+      const char *e = std::getenv("QTN_ABSORB");  // tuning switch
+      return !(e && e[0] == '0');
+    }();
+    auto inside_out = [&](int t) {
+      for (int u : s.tensors[t].vars)
+        if (std::find(out.begin(), out.end(), u) == out.end()) return false;
+      return true;
+    };
     if (o.fuse_chains) {
       const int rI = (int)U.size();
       while (idx + 1 < order.size()) {
         const int w = order[idx + 1];
         if (std::find(out.begin(), out.end(), w) == out.end()) break;
-        bool other = false;
-        for (int t : pool) other |= has(s.tensors[t], w);
-        if (other) break;
+        std::vector<int> others;
+        bool outside = false;
+        for (int t : pool)
+          if (has(s.tensors[t], w)) {
+            others.push_back(t);
+            outside |= !inside_out(t);
+          }
+        if (!others.empty() && (!absorb || outside)) break;
         const int lw = leaf_of[w];
-        if (lw >= 0) {
-          const int rC_next = (int)out.size() - 1;
-          if ((int)inputs.size() >= (rC_next < kSmallRank ? kMaxProgIn : kMaxIn)) break;
-          bool inside = true;
-          for (int u : s.tensors[lw].vars)
-            inside &= std::find(out.begin(), out.end(), u) != out.end();
-          if (!inside) break;
-        }
+        const int rC_next = (int)out.size() - 1;
+        const int limit = rC_next < kSmallRank ? kMaxProgIn : kMaxIn;
+        if ((int)(inputs.size() + others.size()) + (lw >= 0 ? 1 : 0) > limit) break;
+        if (lw >= 0 && !inside_out(lw)) break;
         // Small index spaces are summed in one workgroup and may fuse freely;
         // streaming steps keep enough outputs to fill the chip and sum at
         // most kMaxStreamKappa variables per pass.
@@ -564,6 +580,10 @@ Schedule build_schedule(const Network &net, const std::vector<int> &cut,
         kappa.push_back(w);
         out.erase(std::find(out.begin(), out.end(), w));
         if (lw >= 0) inputs.push_back(lw);
+        for (int t : others) {
+          inputs.push_back(t);
+          pool.erase(std::find(pool.begin(), pool.end(), t));
+        }
         done[w] = 1;
         ++idx;
       }
