@@ -140,6 +140,50 @@ def test_schedule_amplitude_matches_oracle(n, p, seed, k, fuse):
         assert abs(sum(got[b]) - sv) <= 1e-12 * 2.0 ** (-n / 2)
 
 
+def _absorbed_inputs(P):
+    """Inputs of fused steps that are stored intermediates without the first
+    summed variable: tensors of a following bucket taken into the step."""
+    steps, tens = P.export()
+    hits = []
+    for t in range(len(steps)):
+        if steps[t, 2] < 2:
+            continue
+        kap = P.kappa(t)
+        for i in steps[t, 5:5 + steps[t, 1]]:
+            vs = [int(v) for v in tens[i, 4:4 + tens[i, 0]]]
+            if tens[i, 1] == 1 and kap[0] not in vs:
+                assert all(v in kap or v in _step_vars(P, steps, tens, t) for v in vs)
+                hits.append((t, int(i)))
+    return hits
+
+
+def _step_vars(P, steps, tens, t):
+    out = int(steps[t, 0])
+    return [int(v) for v in tens[out, 4:4 + tens[out, 0]]]
+
+
+def test_chain_fusion_absorbs_tensors_inside_the_index_space():
+    # a following bucket whose other tensors lie inside the step's index
+    # space is summed in the same step; the sum over the whole schedule is
+    # still the amplitude (Eq. (1) per bucket, Sec. II B)
+    inst = make_instance(10, 2, 2, 0)
+    P = plan_instance(inst, k=0, seed=0)
+    assert len(_absorbed_inputs(P)) >= 1
+    got = SI.run(P, [0])
+    for b in range(2):
+        sv = Q.statevector_amplitude(10, inst.edges, 2, inst.gamma, inst.beta, inst.bitstrings[b])
+        assert abs(got[b][0] - sv) <= 1e-12 * 2.0 ** (-5)
+    # n=80 p=2 k=16: the last expansion of the order (to a rank-19 tensor that
+    # only the next bucket reads) is not stored any more
+    inst = workload_instance("qaoa_n80_p2_k16")
+    from instances import search_params
+    P = plan_instance(inst, k=16, max_rank=inst.meta["max_rank"], precision="fp32",
+                      **search_params("qaoa_n80_p2_k16"))
+    info = P.info()
+    assert _absorbed_inputs(P)
+    assert info["width"] < info["mf_width"], info
+
+
 def test_workload_plans_meet_caps():
     for name in ["qaoa_n16_p1_k2", "qaoa_n40_p2_b32_k8", "qaoa_n120_p1_b8"]:
         inst = workload_instance(name)
