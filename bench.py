@@ -158,6 +158,23 @@ def _subset_worker(args):
     return vals, time.perf_counter() - t
 
 
+# device memory a wave's workspace may take when the wave size is chosen
+# automatically (one MI355X holds 288 GB)
+WAVE_BUDGET_BYTES = 64 << 30
+
+
+def wave_size(plans, nsl, requested):
+    """Slices per wave: `requested` if given, else the largest power of two
+    up to all nsl slices whose workspace fits WAVE_BUDGET_BYTES in every
+    plan (larger waves amortise the per-wave launches)."""
+    if requested > 0:
+        return min(nsl, requested)
+    S = 1
+    while S < nsl and max(pl.workspace_bytes(2 * S) for pl in plans) <= WAVE_BUDGET_BYTES:
+        S *= 2
+    return S
+
+
 def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
     """One sliced workload: every slice of every bitstring per contraction,
     mixed and FP64 with the same cut, the error of the [0, 1024) subset sums
@@ -175,7 +192,7 @@ def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
     k, B = info["k"], inst.n_bitstrings
     nsl = 1 << k
     f64 = plan_instance(inst, cut_vars=cut, precision="fp64")
-    S = min(nsl, slices_per_wave)
+    S = wave_size((mixed, f64), nsl, slices_per_wave)
     stream = torch.cuda.current_stream().cuda_stream
     info_f = {"flops": 2.0 ** info["log2_flops"]}
     out = {"workload": name, "n": inst.n, "p": inst.p, "bitstrings": B, "k": k,
@@ -270,7 +287,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--slices-per-wave", type=int, default=4096)
+    ap.add_argument("--slices-per-wave", type=int, default=0,
+                    help="slices per wave; 0 picks the largest power of two whose workspace "
+                         "fits %d GiB" % (WAVE_BUDGET_BYTES >> 30))
     ap.add_argument("--no-sliced", action="store_true",
                     help="skip the sliced workloads (n=80 p=2 k=16, n=120 p=1 k=16)")
     ap.add_argument("--sliced-reps", type=int, default=3)
@@ -314,7 +333,7 @@ def main():
     nsl = 1 << k
     B = inst.n_bitstrings
     f64 = plan_instance(inst, cut_vars=cut, precision="fp64")
-    S = min(nsl, args.slices_per_wave)
+    S = wave_size((mixed, f64), nsl, args.slices_per_wave)
     mixed.bind_torch(S)
     f64.bind_torch(S)
     stream = torch.cuda.current_stream().cuda_stream
