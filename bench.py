@@ -163,6 +163,14 @@ def _subset_worker(args):
 WAVE_BUDGET_BYTES = 64 << 30
 
 
+def autotune_summary(plan, stream):
+    st = plan.autotune(stream=stream)
+    print("# autotune: kept %d, whole contraction %.1f us with the choices, %.1f us with the defaults" %
+          (st["kept"], st["whole_tuned_us"], st["whole_default_us"]), file=sys.stderr, flush=True)
+    return {"kept": int(st["kept"]), "whole_tuned_us": st["whole_tuned_us"],
+            "whole_default_us": st["whole_default_us"], "steps": int(st["steps"])}
+
+
 def wave_size(plans, nsl, requested):
     """Slices per wave: `requested` if given, else the largest power of two
     up to all nsl slices whose workspace fits WAVE_BUDGET_BYTES in every
@@ -177,8 +185,9 @@ def wave_size(plans, nsl, requested):
 
 def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
     """One sliced workload: every slice of every bitstring per contraction,
-    mixed and FP64 with the same cut, the error of the [0, 1024) subset sums
-    against the oracle, and the oracle's slice rate on that subset."""
+    mixed and FP64 with the same cut (each autotuned before its timed
+    region), the error of the [0, 1024) subset sums against the oracle, and
+    the oracle's slice rate on that subset."""
     import torch
     from instances import search_params, workload_instance
     from paper_2010_14962_amd import plan_instance
@@ -203,6 +212,7 @@ def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
     res = {}
     for tag, plan in (("mixed", mixed), ("fp64", f64)):
         plan.bind_torch(S)
+        tune = autotune_summary(plan, stream)
         plan.set_graphs(True)
         plan.contract(0, nsl, stream)           # capture and warm-up
         torch.cuda.synchronize()
@@ -216,7 +226,7 @@ def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
                     "ms_per_step": 1e3 * el / reps,
                     # 1: some intermediate in the 64-bit form, rescaling kernels;
                     # 0: every tensor complex128, the FP64 kernels
-                    "rescaled": int(plan.info()["rescaled"])}
+                    "rescaled": int(plan.info()["rescaled"]), "autotune": tune}
         print("# %s %s: %.1f ms per contraction of %d slice instances" %
               (name, tag, 1e3 * el / reps, B * nsl), file=sys.stderr, flush=True)
         if tag == "mixed":

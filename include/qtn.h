@@ -302,9 +302,13 @@ int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
 /*
  * Autotuner of the launch configuration: for every grid-wide streaming step
  * of the bound plan it times (HIP events on `stream`, 5 launches each) the
- * block count over the chip (256, 512, 1024, 2048) and, where the LDS-staged
- * kernel applies, that kernel against the direct one, and keeps the fastest
- * for later contractions.  cache_path (or NULL): a text file of known choices,
+ * block count over the chip (256, 512, 1024, 2048, 4096) and, where the
+ * LDS-staged kernel applies, that kernel against the direct one, and takes
+ * the fastest.  Steps run alone there but share launches in a contraction,
+ * so the choices are kept for later contractions only if a whole
+ * contraction of the first wave (5 direct-launch runs each) is faster with
+ * them than with the defaults; otherwise the defaults stay.
+ * cache_path (or NULL): a text file of known choices,
  * one line per step signature ("<hex signature> <blocks> <direct> <us>"); steps
  * found there are not measured, new choices are appended.  Runs one
  * contraction of the first wave first (its results are discarded) and leaves
@@ -320,6 +324,9 @@ typedef struct {
   uint32_t cached;     /* steps whose choice came from the cache           */
   double default_us;   /* summed time of the measured steps, default config */
   double tuned_us;     /* the same steps with the chosen configuration     */
+  double whole_default_us; /* one contraction of the first wave, defaults   */
+  double whole_tuned_us;   /* the same with the chosen configurations       */
+  uint32_t kept;       /* 1: the choices are in use; 0: the defaults are    */
 } qtn_tune_stats;
 int qtn_plan_autotune(qtn_plan_t *plan, void *stream, const char *cache_path, qtn_tune_stats *stats);
 

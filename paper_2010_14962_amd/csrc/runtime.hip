@@ -2684,7 +2684,7 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
     // the state is rebuilt by the next contraction)
     double best_us = 0, default_us = 0;
     StepTune best;
-    for (uint32_t target : {256u, 512u, 1024u, 2048u})
+    for (uint32_t target : {256u, 512u, 1024u, 2048u, 4096u})
       for (int so = 0; so < (d.tiled_lds ? 2 : 1); ++so) {
         StepTune t;
         t.target = target;
@@ -2714,6 +2714,40 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
     st->default_us += default_us;
     st->tuned_us += best_us;
     learned.push_back({sig, {best, best_us}});
+  }
+  // The steps were timed alone; in a contraction the steps of one launch
+  // level share a launch and run together, so a choice that is faster alone
+  // can be slower there.  The choices stay only if a whole contraction of
+  // the first wave is faster with them.
+  bool differs = false;
+  for (const StepTune &t : D->tune) differs |= t.target != StepTune().target || t.stream_only;
+  st->kept = differs ? 1u : 0u;
+  if (!rc && differs) {
+    auto whole = [&](double *us) -> int {
+      if (int r = run_waves<SCALE>(P, D, 0, cnt, stream, false)) return r;  // warm-up
+      constexpr int R = 5;
+      if (hipEventRecord(e0, stream) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+      for (int r = 0; r < R; ++r)
+        if (int w = run_waves<SCALE>(P, D, 0, cnt, stream, false)) return w;
+      if (hipEventRecord(e1, stream) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventRecord");
+      if (int w = wait_stream(stream, "qtn_plan_autotune")) return w;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return hip_fail(hipGetLastError(), "hipEventElapsedTime");
+      *us = 1e3 * ms / R;
+      return QTN_OK;
+    };
+    const std::vector<StepTune> tuned = D->tune;
+    rc = whole(&st->whole_tuned_us);
+    if (!rc) {
+      D->tune.assign(sch.steps.size(), StepTune());
+      rc = whole(&st->whole_default_us);
+    }
+    if (!rc && st->whole_tuned_us < st->whole_default_us) {
+      D->tune = tuned;
+    } else {
+      D->tune.assign(sch.steps.size(), StepTune());
+      st->kept = 0;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

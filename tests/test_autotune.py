@@ -1,6 +1,7 @@
 """The autotuner of the launch configuration (qtn_plan_autotune): it times
-the alternatives of every streaming step, keeps the fastest, reuses a cache of
-earlier choices, and leaves the amplitudes unchanged (the block partition of
+the alternatives of every streaming step, keeps the fastest where a whole
+contraction gains, reuses a cache of earlier choices, and leaves the
+amplitudes unchanged (the block partition of
 a step changes, the arithmetic of its outputs does not)."""
 import pytest
 
@@ -24,6 +25,9 @@ def test_autotune_keeps_results_and_caches(precision, tmp_path):
     print("autotune", st, flush=True)
     assert st["steps"] > 0 and st["measured"] >= st["steps"] and st["cached"] == 0
     assert st["tuned_us"] <= st["default_us"]
+    # the choices stay only where a whole contraction is faster with them
+    if st["kept"]:
+        assert st["whole_tuned_us"] < st["whole_default_us"]
     after = [p.value() for p in plan.contract(0, 1, stream)]
     for a, b in zip(after, before):
         assert abs(a - b) <= 1e-12 * abs(b)
@@ -34,4 +38,6 @@ def test_autotune_keeps_results_and_caches(precision, tmp_path):
     other.bind_torch(1)
     st2 = other.autotune(cache, stream)
     assert st2["measured"] == 0 and st2["cached"] == st["steps"]
-    assert [p.value() for p in other.contract(0, 1, stream)] == after
+    # (whether the cached choices stay is decided by timing again)
+    for a, b in zip([p.value() for p in other.contract(0, 1, stream)], after):
+        assert abs(a - b) <= 1e-12 * abs(b)
