@@ -164,11 +164,25 @@ WAVE_BUDGET_BYTES = 64 << 30
 
 
 def autotune_summary(plan, stream):
+    """Runs the library's autotuner (per-step launch configurations, kept
+    only if a whole contraction gains, then graph replay or direct launches,
+    whichever is faster) and returns what it chose."""
     st = plan.autotune(stream=stream)
-    print("# autotune: kept %d, whole contraction %.1f us with the choices, %.1f us with the defaults" %
-          (st["kept"], st["whole_tuned_us"], st["whole_default_us"]), file=sys.stderr, flush=True)
+    print("# autotune: kept %d (whole contraction %.1f us with the choices, %.1f us with the "
+          "defaults); %s (%.1f us graph replay, %.1f us direct)" %
+          (st["kept"], st["whole_tuned_us"], st["whole_default_us"],
+           "graph replay" if st["graphs"] else "direct launches", st["graph_us"], st["direct_us"]),
+          file=sys.stderr, flush=True)
+    plan.bench_graphs = bool(st["graphs"])
     return {"kept": int(st["kept"]), "whole_tuned_us": st["whole_tuned_us"],
-            "whole_default_us": st["whole_default_us"], "steps": int(st["steps"])}
+            "whole_default_us": st["whole_default_us"], "steps": int(st["steps"]),
+            "launch_mode": "graph replay" if st["graphs"] else "direct launches",
+            "graph_us": st["graph_us"], "direct_us": st["direct_us"]}
+
+
+def bench_graphs(plan) -> bool:
+    """Launch mode of the timed regions: the autotuner's choice, else graphs."""
+    return getattr(plan, "bench_graphs", True)
 
 
 def wave_size(plans, nsl, requested):
@@ -183,7 +197,7 @@ def wave_size(plans, nsl, requested):
     return S
 
 
-def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
+def sliced_row(name, seed, slices_per_wave, reps, with_cpu, autotune=True):
     """One sliced workload: every slice of every bitstring per contraction,
     mixed and FP64 with the same cut (each autotuned before its timed
     region), the error of the [0, 1024) subset sums against the oracle, and
@@ -212,8 +226,8 @@ def sliced_row(name, seed, slices_per_wave, reps, with_cpu):
     res = {}
     for tag, plan in (("mixed", mixed), ("fp64", f64)):
         plan.bind_torch(S)
-        tune = autotune_summary(plan, stream)
-        plan.set_graphs(True)
+        tune = autotune_summary(plan, stream) if autotune else None
+        plan.set_graphs(bench_graphs(plan))
         plan.contract(0, nsl, stream)           # capture and warm-up
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -303,6 +317,8 @@ def main():
     ap.add_argument("--no-sliced", action="store_true",
                     help="skip the sliced workloads (n=80 p=2 k=16, n=120 p=1 k=16)")
     ap.add_argument("--sliced-reps", type=int, default=3)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the autotuner (graph replay, default launch configurations)")
     ap.add_argument("--sliced-child", default=None,
                     help="internal: run one sliced workload and print its JSON object")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -321,7 +337,8 @@ def main():
     torch.cuda.set_device(0)
     if args.sliced_child:
         print(json.dumps(sliced_row(args.sliced_child, args.seed, args.slices_per_wave,
-                                    args.sliced_reps, not args.no_cpu_baseline)), flush=True)
+                                    args.sliced_reps, not args.no_cpu_baseline,
+                                    not args.no_autotune)), flush=True)
         return
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib << 20
@@ -349,12 +366,16 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     print("# workload %s k=%d width=%d steps=%d B=%d S=%d plan %.3fs" %
           (args.workload, k, info["width"], info["n_steps"], B, S, plan_s), file=sys.stderr, flush=True)
+    # launch configurations and launch mode, measured before any timed region
+    tune = None
+    if not args.no_autotune:
+        tune = {"mixed": autotune_summary(mixed, stream), "fp64": autotune_summary(f64, stream)}
 
     def run_pipelined(plan, steps, warmup):
         """Timed region: `steps` asynchronous contractions enqueued back to
-        back on the stream (graph replays), each copying its partials to its
-        own slot of a pinned host buffer, then one synchronisation."""
-        plan.set_graphs(True)
+        back on the stream, each copying its partials to its own slot of a
+        pinned host buffer, then one synchronisation."""
+        plan.set_graphs(bench_graphs(plan))
         buf = torch.zeros((steps + warmup, B, 4), dtype=torch.float64).pin_memory()
         for i in range(warmup):
             plan.contract_async(0, nsl, buf[i].data_ptr(), stream)
@@ -372,7 +393,7 @@ def main():
         """Timed region: `steps` contractions bracketed by device syncs.  With
         `timing`, kernels are launched directly (no graph replay) and each
         streaming-step launch is bracketed by HIP events on its stream."""
-        plan.set_graphs(not timing)
+        plan.set_graphs(bench_graphs(plan) and not timing)
         for _ in range(warmup):
             plan.contract(0, nsl, stream)
         if timing:
@@ -388,11 +409,11 @@ def main():
         if timing:
             tm["steps"] = {st: plan.step_timing(st) for st in range(plan.info()["n_steps"])}
             plan.set_timing(False)
-        plan.set_graphs(True)
+        plan.set_graphs(bench_graphs(plan))
         return el, [p.value() for p in out], tm
 
-    # value: one synchronous qtn_contract per step (graph replay), nothing
-    # else in the timed region
+    # value: one synchronous qtn_contract per step (in the autotuned launch
+    # mode), nothing else in the timed region
     el, amps, _ = run(mixed, args.steps, args.warmup, False)
     print("# mixed, synchronous calls: %.3f ms/step" % (1e3 * el / args.steps), file=sys.stderr, flush=True)
     # the same steps enqueued back to back with qtn_contract_async
@@ -455,7 +476,9 @@ def main():
                                 "two 28-bit mantissas) with per-instance power-of-two rescaling, "
                                 "fp64 arithmetic, fp64 compensated slice sum"},
         "slices_per_sec": slices_per_s,
-        "timing": "one synchronous qtn_contract per step (graph replay, partials in host memory)",
+        "timing": "one synchronous qtn_contract per step (%s, partials in host memory)" %
+                  ("graph replay" if bench_graphs(mixed) else "direct launches"),
+        "autotune": tune,
         "pipelined_ms_per_step": 1e3 * el_pipe / args.steps,
         "fp64": {"amplitudes_per_sec": B * n64 / el64, "slices_per_sec": B * nsl * n64 / el64,
                  "ms_per_step": 1e3 * el64 / n64},
@@ -487,6 +510,8 @@ def main():
                    "--slices-per-wave", str(args.slices_per_wave), "--sliced-reps", str(args.sliced_reps)]
             if args.no_cpu_baseline:
                 cmd.append("--no-cpu-baseline")
+            if args.no_autotune:
+                cmd.append("--no-autotune")
             try:
                 r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
                 sys.stderr.write(r.stderr)

@@ -307,7 +307,10 @@ int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
  * the fastest.  Steps run alone there but share launches in a contraction,
  * so the choices are kept for later contractions only if a whole
  * contraction of the first wave (5 direct-launch runs each) is faster with
- * them than with the defaults; otherwise the defaults stay.
+ * them than with the defaults; otherwise the defaults stay.  Last, the
+ * launch mode (qtn_plan_set_graphs) is set to whichever of graph replay and
+ * direct launches runs a synchronous qtn_contract of the first wave faster
+ * (10 calls each); a later qtn_plan_set_graphs overrides it.
  * cache_path (or NULL): a text file of known choices,
  * one line per step signature ("<hex signature> <blocks> <direct> <us>"); steps
  * found there are not measured, new choices are appended.  Runs one
@@ -327,6 +330,9 @@ typedef struct {
   double whole_default_us; /* one contraction of the first wave, defaults   */
   double whole_tuned_us;   /* the same with the chosen configurations       */
   uint32_t kept;       /* 1: the choices are in use; 0: the defaults are    */
+  double graph_us;     /* synchronous contraction of the first wave, graph  */
+  double direct_us;    /* the same, kernels launched directly               */
+  uint32_t graphs;     /* the launch mode kept: 1 graph replay, 0 direct    */
 } qtn_tune_stats;
 int qtn_plan_autotune(qtn_plan_t *plan, void *stream, const char *cache_path, qtn_tune_stats *stats);
 

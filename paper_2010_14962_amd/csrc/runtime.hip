@@ -2752,6 +2752,29 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
+  // Launch mode: the whole contraction of the first wave through the public
+  // call (synchronous, partials to host memory), replayed from a captured
+  // graph against launched directly; the faster mode stays.
+  {
+    std::vector<qtn_partial> part(P->net.B);
+    auto whole_call = [&](bool graphs, double *us) -> int {
+      D->use_graphs = graphs;
+      drop_graph(D);
+      for (int r = 0; r < 2; ++r)   // capture (with graphs) and warm-up
+        if (int w = contract_impl(P, 0, cnt, stream, part.data(), false)) return w;
+      constexpr int R = 10;
+      const auto t0 = std::chrono::steady_clock::now();
+      for (int r = 0; r < R; ++r)
+        if (int w = contract_impl(P, 0, cnt, stream, part.data(), false)) return w;
+      *us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count() / R;
+      return QTN_OK;
+    };
+    if (int w = whole_call(true, &st->graph_us)) return w;
+    if (int w = whole_call(false, &st->direct_us)) return w;
+    D->use_graphs = st->graph_us <= st->direct_us;
+    drop_graph(D);
+    st->graphs = D->use_graphs ? 1u : 0u;
+  }
   // the measurements raised exponent words: start the next contraction clean
   if (SCALE && D->L.exp_bytes) HIP_TRY(hipMemsetAsync(D->ws + D->L.data_bytes, 0, D->L.exp_bytes, stream));
   if (int w = wait_stream(stream, "qtn_plan_autotune")) return w;

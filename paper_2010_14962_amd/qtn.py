@@ -79,7 +79,8 @@ class QtnGate(ctypes.Structure):
 class QtnTuneStats(ctypes.Structure):
     _fields_ = [("steps", c_uint32), ("measured", c_uint32), ("cached", c_uint32),
                 ("default_us", c_double), ("tuned_us", c_double),
-                ("whole_default_us", c_double), ("whole_tuned_us", c_double), ("kept", c_uint32)]
+                ("whole_default_us", c_double), ("whole_tuned_us", c_double), ("kept", c_uint32),
+                ("graph_us", c_double), ("direct_us", c_double), ("graphs", c_uint32)]
 
 
 class QtnError(RuntimeError):

@@ -33,6 +33,12 @@ def test_autotune_keeps_results_and_caches(precision, tmp_path):
         assert abs(a - b) <= 1e-12 * abs(b)
     again = [p.value() for p in plan.contract(0, 1, stream)]
     assert again == after
+    # the launch mode it chose was measured both ways; both give the same bits
+    assert st["graphs"] in (0, 1) and st["graph_us"] > 0 and st["direct_us"] > 0
+    assert (st["graph_us"] <= st["direct_us"]) == bool(st["graphs"])
+    for graphs in (True, False):
+        plan.set_graphs(graphs)
+        assert [p.value() for p in plan.contract(0, 1, stream)] == after
     # a second plan of the same workload takes every choice from the cache
     other = plan_instance(inst, k=0, precision=precision)
     other.bind_torch(1)
