@@ -305,9 +305,9 @@ int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
  * block count over the chip (256, 512, 1024, 2048, 4096) and, where the
  * LDS-staged kernel applies, that kernel against the direct one, and takes
  * the fastest.  Steps run alone there but share launches in a contraction,
- * so the choices are kept for later contractions only if a whole
- * contraction of the first wave (5 direct-launch runs each) is faster with
- * them than with the defaults; otherwise the defaults stay.  Last, the
+ * so, starting from the defaults, each step's choice (largest gain first)
+ * is kept for later contractions only if a whole contraction of the first
+ * wave (5 direct-launch runs) is then at least 1% faster.  Last, the
  * launch mode (qtn_plan_set_graphs) is set to whichever of graph replay and
  * direct launches runs a synchronous qtn_contract of the first wave faster
  * (10 calls each); a later qtn_plan_set_graphs overrides it.
@@ -328,8 +328,8 @@ typedef struct {
   double default_us;   /* summed time of the measured steps, default config */
   double tuned_us;     /* the same steps with the chosen configuration     */
   double whole_default_us; /* one contraction of the first wave, defaults   */
-  double whole_tuned_us;   /* the same with the chosen configurations       */
-  uint32_t kept;       /* 1: the choices are in use; 0: the defaults are    */
+  double whole_tuned_us;   /* the same with the choices kept                */
+  uint32_t kept;       /* steps whose measured choice is kept               */
   double graph_us;     /* synchronous contraction of the first wave, graph  */
   double direct_us;    /* the same, kernels launched directly               */
   uint32_t graphs;     /* the launch mode kept: 1 graph replay, 0 direct    */

@@ -2663,6 +2663,7 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   std::vector<std::pair<uint64_t, std::pair<StepTune, double>>> learned;
+  std::vector<std::pair<double, int>> gain;   // (time saved alone, step)
   int rc = QTN_OK;
   for (const LaunchGroup &G : X.launches) {
     if (G.kind != 1) continue;
@@ -2677,6 +2678,7 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
     if (hit != cache.end()) {
       D->tune[s_] = hit->second;
       ++st->cached;
+      gain.push_back({0.0, s_});
       continue;
     }
     // (timing of garbage inputs: every launch reads only its own operands'
@@ -2714,15 +2716,15 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
     st->default_us += default_us;
     st->tuned_us += best_us;
     learned.push_back({sig, {best, best_us}});
+    gain.push_back({default_us - best_us, s_});
   }
   // The steps were timed alone; in a contraction the steps of one launch
   // level share a launch and run together, so a choice that is faster alone
-  // can be slower there.  The choices stay only if a whole contraction of
-  // the first wave is faster with them.
-  bool differs = false;
-  for (const StepTune &t : D->tune) differs |= t.target != StepTune().target || t.stream_only;
-  st->kept = differs ? 1u : 0u;
-  if (!rc && differs) {
+  // can be slower there.  Starting from the defaults, each step's choice
+  // (largest gain alone first) stays only if a whole contraction of the
+  // first wave is then at least 1% faster.
+  const std::vector<StepTune> chosen = D->tune;
+  if (!rc) {
     auto whole = [&](double *us) -> int {
       if (int r = run_waves<SCALE>(P, D, 0, cnt, stream, false)) return r;  // warm-up
       constexpr int R = 5;
@@ -2736,18 +2738,29 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
       *us = 1e3 * ms / R;
       return QTN_OK;
     };
-    const std::vector<StepTune> tuned = D->tune;
-    rc = whole(&st->whole_tuned_us);
-    if (!rc) {
-      D->tune.assign(sch.steps.size(), StepTune());
-      rc = whole(&st->whole_default_us);
+    std::vector<StepTune> cur(sch.steps.size(), StepTune());
+    D->tune = cur;
+    double cur_us = 0;
+    rc = whole(&cur_us);
+    st->whole_default_us = cur_us;
+    std::stable_sort(gain.begin(), gain.end(),
+                     [](const std::pair<double, int> &a, const std::pair<double, int> &b) { return a.first > b.first; });
+    for (const auto &g : gain) {
+      if (rc) break;
+      const StepTune &c = chosen[g.second];
+      if (c.target == StepTune().target && c.stream_only == StepTune().stream_only) continue;
+      D->tune = cur;
+      D->tune[g.second] = c;
+      double us = 0;
+      if ((rc = whole(&us))) break;
+      if (us < 0.99 * cur_us) {
+        cur = D->tune;
+        cur_us = us;
+        ++st->kept;
+      }
     }
-    if (!rc && st->whole_tuned_us < st->whole_default_us) {
-      D->tune = tuned;
-    } else {
-      D->tune.assign(sch.steps.size(), StepTune());
-      st->kept = 0;
-    }
+    D->tune = cur;
+    st->whole_tuned_us = cur_us;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -25,9 +25,12 @@ def test_autotune_keeps_results_and_caches(precision, tmp_path):
     print("autotune", st, flush=True)
     assert st["steps"] > 0 and st["measured"] >= st["steps"] and st["cached"] == 0
     assert st["tuned_us"] <= st["default_us"]
-    # the choices stay only where a whole contraction is faster with them
+    # choices stay only where a whole contraction gets faster with them
+    assert st["kept"] <= st["steps"]
     if st["kept"]:
         assert st["whole_tuned_us"] < st["whole_default_us"]
+    else:
+        assert st["whole_tuned_us"] == st["whole_default_us"]
     after = [p.value() for p in plan.contract(0, 1, stream)]
     for a, b in zip(after, before):
         assert abs(a - b) <= 1e-12 * abs(b)
