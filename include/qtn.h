@@ -373,6 +373,12 @@ int qtn_plan_step_timing(const qtn_plan_t *plan, int32_t step, qtn_kernel_timing
  * inside workgroup programs.  NUL-terminated, truncated to `capacity`. */
 int qtn_plan_step_kernel(const qtn_plan_t *plan, int32_t step, char *name, uint32_t capacity);
 
+/* Launch configuration in use for grid-wide step `step` (qtn_plan_autotune's
+ * kept choice, else the default): *blocks = the block count over the chip it
+ * targets (1024 by default), *direct = 1 when the direct kernel runs a step
+ * that could stage its operands in LDS.  Host-side; no device work. */
+int qtn_plan_step_tune(const qtn_plan_t *plan, int32_t step, uint32_t *blocks, int32_t *direct);
+
 /* ---------------------------------------------------------------------------
  * Learned cut-set cost model.  Not part of the paper: it ranks candidate cut
  * sets for the search of Sec. III B by predicted log2 cost and peak rank;

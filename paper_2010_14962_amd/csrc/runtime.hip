@@ -3188,6 +3188,21 @@ extern "C" int qtn_plan_step_timing(const qtn_plan_t *P, int32_t step, qtn_kerne
   return QTN_OK;
 }
 
+extern "C" int qtn_plan_step_tune(const qtn_plan_t *P, int32_t step, uint32_t *blocks, int32_t *direct) {
+  if (!P || !P->dev || !blocks || !direct) {
+    set_error("bind a workspace first");
+    return QTN_ESTATE;
+  }
+  if (step < 0 || (size_t)step >= P->sched.steps.size()) {
+    set_error("step out of range");
+    return QTN_ERANGE;
+  }
+  const StepTune t = P->dev->tune.empty() ? StepTune() : P->dev->tune[step];
+  *blocks = t.target;
+  *direct = t.stream_only ? 1 : 0;
+  return QTN_OK;
+}
+
 extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *name, uint32_t capacity) {
   if (!P || !P->dev || !name || capacity == 0) {
     set_error("bind a workspace first");
@@ -3206,13 +3221,15 @@ extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *nam
       const bool sc = P->scaled[D->mode];
       const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
       const std::string tf = sc ? "true" : "false";
+      // the autotuner may have chosen the direct kernel for a staged step
+      const bool tiled = d.tiled_lds && !(!D->tune.empty() && D->tune[step].stream_only);
       if (!streaming)
         k = "step_small<" + tf + ">";
       else
-        k = std::string(d.tiled_lds ? "step_tiled<" : "step_stream<") + tf + ", " +
+        k = std::string(tiled ? "step_tiled<" : "step_stream<") + tf + ", " +
             std::to_string(d.nk) + ", " + std::to_string(d.nvary) + ", " +
             std::to_string(d.nf32 <= d.nvary ? d.nf32 : 0) +
-            (d.tiled_lds ? (d.tiled_fold == 0 ? ", true>" : ", false>") : ">") +
+            (tiled ? (d.tiled_fold == 0 ? ", true>" : ", false>") : ">") +
             (d.dot ? " + closing-chain reduction" : "");
     }
   std::strncpy(name, k.c_str(), capacity - 1);

@@ -99,7 +99,7 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_cost_features", "qtn_cost_exact", "qtn_mlp_create", "qtn_mlp_destroy",
            "qtn_mlp_num_params", "qtn_mlp_get_params", "qtn_mlp_set_params", "qtn_mlp_get_grads",
            "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search",
-           "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_contract_async",
+           "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_plan_step_tune", "qtn_contract_async",
            "qtn_contract_ranges", "qtn_plan_fingerprint", "qtn_plan_inject_faults",
            "qtn_contract_noalloc", "qtn_batch_contract", "qtn_plan_autotune", "qtn_plan_circuit"]
 COST_FEATURES = 32
@@ -141,6 +141,7 @@ def lib():
     L.qtn_plan_timing.argtypes = [c_void_p, POINTER(QtnKernelTiming)]
     L.qtn_plan_step_timing.argtypes = [c_void_p, c_int32, POINTER(QtnKernelTiming)]
     L.qtn_plan_step_kernel.argtypes = [c_void_p, c_int32, c_char_p, c_uint32]
+    L.qtn_plan_step_tune.argtypes = [c_void_p, c_int32, POINTER(c_uint32), POINTER(c_int32)]
     L.qtn_last_error.argtypes = []
     L.qtn_last_error.restype = c_char_p
     pf, pu32 = POINTER(ctypes.c_float), POINTER(c_uint32)
@@ -296,6 +297,12 @@ class Plan:
         buf = ctypes.create_string_buffer(128)
         _check(lib().qtn_plan_step_kernel(self._h, step, buf, len(buf)))
         return buf.value.decode()
+
+    def step_tune(self, step: int) -> dict:
+        """Launch configuration in use for a grid-wide step (autotuned or default)."""
+        blocks, direct = c_uint32(0), c_int32(0)
+        _check(lib().qtn_plan_step_tune(self._h, step, byref(blocks), byref(direct)))
+        return {"blocks": blocks.value, "direct": bool(direct.value)}
 
     def contract_async(self, slice_lo: int, slice_hi: int, out_ptr: int,
                        stream: Optional[int] = None) -> None:
