@@ -303,8 +303,8 @@ int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
  * Autotuner of the launch configuration: for every grid-wide streaming step
  * of the bound plan it times (HIP events on `stream`, 5 launches each) the
  * block count over the chip (256, 512, 1024, 2048, 4096) and, where the
- * LDS-staged kernel applies, that kernel against the direct one, and takes
- * the fastest.  Steps run alone there but share launches in a contraction,
+ * LDS-staged kernel applies, that kernel against the direct one and (for
+ * steps that allow it) the row-paired staged one, and takes the fastest.  Steps run alone there but share launches in a contraction,
  * so, starting from the defaults, each step's choice (largest gain first)
  * is kept for later contractions only if a whole contraction of the first
  * wave (5 direct-launch runs) is then at least 1% faster.  Last, the
@@ -312,7 +312,7 @@ int qtn_plan_set_graphs(qtn_plan_t *plan, int enable);
  * direct launches runs a synchronous qtn_contract of the first wave faster
  * (10 calls each); a later qtn_plan_set_graphs overrides it.
  * cache_path (or NULL): a text file of known choices,
- * one line per step signature ("<hex signature> <blocks> <direct> <us>"); steps
+ * one line per step signature ("<hex signature> <blocks> <variant> <us>"); steps
  * found there are not measured, new choices are appended.  Runs one
  * contraction of the first wave first (its results are discarded) and leaves
  * the workspace ready for the next call; drops the captured graph.  Not while
@@ -375,9 +375,11 @@ int qtn_plan_step_kernel(const qtn_plan_t *plan, int32_t step, char *name, uint3
 
 /* Launch configuration in use for grid-wide step `step` (qtn_plan_autotune's
  * kept choice, else the default): *blocks = the block count over the chip it
- * targets (1024 by default), *direct = 1 when the direct kernel runs a step
- * that could stage its operands in LDS.  Host-side; no device work. */
-int qtn_plan_step_tune(const qtn_plan_t *plan, int32_t step, uint32_t *blocks, int32_t *direct);
+ * targets (1024 by default); *variant = 0 for the default kernel, 1 when the
+ * direct kernel runs a step that could stage its operands in LDS, 2 for the
+ * row-paired staged kernel (each thread sums two rows that share the staged
+ * runs of operand 0).  Host-side; no device work. */
+int qtn_plan_step_tune(const qtn_plan_t *plan, int32_t step, uint32_t *blocks, int32_t *variant);
 
 /* ---------------------------------------------------------------------------
  * Learned cut-set cost model.  Not part of the paper: it ranks candidate cut

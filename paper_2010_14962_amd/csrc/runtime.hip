@@ -59,10 +59,12 @@ struct PStep {
   uint32_t wg_flags;      // in a workgroup program: 1 = every operand in LDS
   int tiled_fold;         // step_tiled: operand staged as complex128 times the
                           // kappa coefficient, or -1
+  uint32_t tiled_pair;    // > 0: step_tiled_pair may run it with this much more LDS
   uint32_t dot;           // 1: reduce the outputs against the closing chain's
                           //    gate factors (DotArgs) instead of storing them
   uint32_t dot_lds;       // dynamic LDS bytes of that epilogue
   const void *dotp;       // DotArgs in device memory (set at launch)
+  uint32_t pad_[2];       // size a multiple of 16 bytes
 };
 static_assert(sizeof(PStep) % 16 == 0, "PStep layout");
 
@@ -134,6 +136,7 @@ struct GroupArgs {
 struct StepTune {
   uint32_t target = 1024;   // blocks over the chip
   bool stream_only = false; // run step_stream even where step_tiled applies
+  bool pair = false;        // run step_tiled_pair where it applies
 };
 
 struct DeviceState {
@@ -1121,6 +1124,30 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
   stream_body<SCALE, NK, NV, NF>(d, nb, ns, s_lo, jspan, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
 }
 
+// Visiting order of the four low row bits of a 16-row chunk of step_tiled,
+// 2 bits per position (innermost first): bits that large operands lack come
+// first, so that their staged runs serve consecutive rows; the weight of a
+// bit is the number of staged elements of the operands that lack it (ties:
+// lower bit first).  The host uses it to decide row pairing.
+__host__ __device__ inline uint32_t tiled_row_order(const PStep &d) {
+  const uint32_t cb = d.rC >= 32 ? ~0u : ((1u << d.rC) - 1u);
+  uint32_t wbit[4] = {0u, 0u, 0u, 0u};
+  for (int v = 0; v < d.nvary && v < 4; ++v) {
+    const uint32_t cm = d.in[v].mask & cb;
+    const uint32_t rdep = cm >> 8;
+    const uint32_t n = 1u << (__builtin_popcount(d.in[v].mask >> d.rC) + __builtin_popcount(cm & 255u));
+    for (int b = 0; b < 4; ++b)
+      if (!((rdep >> b) & 1u)) wbit[b] += n;
+  }
+  uint32_t rord = 0;
+  for (int i = 0; i < 4; ++i) {
+    uint32_t rank = 0;
+    for (int b = 0; b < 4; ++b) rank += (wbit[b] > wbit[i] || (wbit[b] == wbit[i] && b < i)) ? 1u : 0u;
+    rord |= (uint32_t)i << (2u * rank);
+  }
+  return rord;
+}
+
 // Streaming steps whose varying operands are re-read many times per row.
 // For a row of 256 consecutive output elements, operand v is touched at
 // base_v(row) + pext(c & 255, mask) + (pext(kappa, kmask) << pc): 2^nkv runs
@@ -1128,10 +1155,14 @@ __global__ __launch_bounds__(256) void step_stream(const PStep d, uint32_t nb, u
 // low output bits at the bottom of the operand index).  The block stages
 // those runs in LDS once per row and sums over kappa from LDS, so each
 // operand element is fetched once per row instead of once per use.
-template <bool SCALE, int NK, int NV, int NF, bool FOLD>
+template <bool SCALE, int NK, int NV, int NF, bool FOLD, bool PAIR = false>
 __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t ns, uint64_t s_lo,
                                            uint32_t jspan, uint32_t bx, uint32_t by, uint32_t gx,
                                            uint32_t gy) {
+  // PAIR (FOLD steps, jspan >= 16): each thread sums two rows that differ in
+  // the innermost row bit of the visiting order, which operand 0 lacks and
+  // every other operand has; operand 0's staged runs and LDS reads serve
+  // both rows, the others are staged twice (second regions after the first).
   constexpr uint32_t NKAP = 1u << NK;
   extern __shared__ __align__(16) char stage[];
   __shared__ uint32_t s_mid[NV][16];
@@ -1172,27 +1203,21 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
     soff[v] = bytes;
     bytes += (1u << (nkv[v] + nlo[v])) * 16u;   // staged as complex128
   }
-  // row bits each operand depends on, and the visiting order of the four
-  // low row bits: bits that large operands lack innermost, so that their
-  // staged runs serve consecutive rows (weights: run elements saved)
-  uint32_t rdep[NV];
-  uint32_t wbit[4] = {0u, 0u, 0u, 0u};
+  uint32_t soff2[NV];   // PAIR: the second row's runs of operands 1..NV-1
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    rdep[v] = (d.in[v].mask & cb) >> 8;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (!((rdep[v] >> b) & 1u)) wbit[b] += 1u << (nkv[v] + nlo[v]);
+    soff2[v] = soff[v];
+    if (PAIR && v > 0) {
+      soff2[v] = bytes;
+      bytes += (1u << (nkv[v] + nlo[v])) * 16u;
+    }
   }
-  uint32_t rord = 0;   // 2 bits per position: the row bit visited there
+  // row bits each operand depends on, and the visiting order of the four
+  // low row bits (2 bits per position: the row bit visited there)
+  uint32_t rdep[NV];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    // position of bit i: the number of heavier bits (ties: lower bit first)
-    uint32_t rank = 0;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) rank += (wbit[b] > wbit[i] || (wbit[b] == wbit[i] && b < i)) ? 1u : 0u;
-    rord |= (uint32_t)i << (2u * rank);
-  }
+  for (int v = 0; v < NV; ++v) rdep[v] = (d.in[v].mask & cb) >> 8;
+  const uint32_t rord = tiled_row_order(d);
   constexpr int fold = FOLD ? 0 : -1;
   const uint64_t Q = (uint64_t)nb * ns;
   const uint32_t rows = (1u << d.rC) >> 8;
@@ -1231,6 +1256,12 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
       const lds_c128 c = ((const QTN_LDS lds_c128 *)(stage + soff[v]))[idx];
       return make_double2(c.x, c.y);
     };
+    // PAIR: operand v (v >= 1) for the second row
+    auto opnd2 = [&](int v, uint32_t k) __attribute__((always_inline)) {
+      const uint32_t idx = s_kap[v][k] + lo[v];
+      const lds_c128 c = ((const QTN_LDS lds_c128 *)(stage + soff2[v]))[idx];
+      return make_double2(c.x, c.y);
+    };
     // coefficient x operands 0 .. upto-1 at position k (the folded operand
     // carries the coefficient)
     auto head = [&](uint32_t k, int upto) __attribute__((always_inline)) {
@@ -1257,6 +1288,121 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
       // the index part of the row bits above the lowest four
       const char *cbase[NV];
       uint32_t key[NV];
+      if constexpr (PAIR) {
+        // the two rows' outputs: stored, or reduced against the closing chain
+        auto finish = [&](uint32_t row, double2 acc) __attribute__((always_inline)) {
+          if (dot) {
+            if (SCALE) {
+              acc.x = ldexp(acc.x, -sh);
+              acc.y = ldexp(acc.y, -sh);
+            }
+            dot_add(DA, dsv, DS, dsw[row - u * jspan], row, acc);
+          } else if (SCALE) {
+            wmax = max(wmax, store_scaled(op, of, ((uint64_t)row << 8) | t, acc, sh));
+          } else {
+            store_g(op, of, ((uint64_t)row << 8) | t, acc);
+          }
+        };
+        // operand v's runs for `row`, as complex128, at byte `off` of the stage
+        auto stage_op = [&](int v, uint32_t row, uint32_t off) __attribute__((always_inline)) {
+          constexpr uint32_t esz_f = 8u, esz_d = 16u;
+          const uint32_t esz = v < NF ? esz_f : esz_d;
+          const char *rb = cbase[v] + (uint64_t)__builtin_amdgcn_readfirstlane(s_mid[v][row & 15u]) * esz;
+          const uint32_t n = 1u << (nkv[v] + nlo[v]);
+          const uint32_t lmask = (1u << nlo[v]) - 1u;
+          QTN_LDS lds_c128 *dst = (QTN_LDS lds_c128 *)(stage + off);
+          for (uint32_t e = t; e < n; e += 512) {
+            const bool two = e + 256 < n;
+            const uint32_t g0 = (((e >> nlo[v]) << pc[v]) + (e & lmask)) * esz;
+            const uint32_t e1 = e + 256;
+            const uint32_t g1 = (((e1 >> nlo[v]) << pc[v]) + (e1 & lmask)) * esz;
+            double2 x0, x1 = make_double2(0.0, 0.0);
+            if (v < NF) {
+              const uint64_t w0 = *(const uint64_t *)(rb + g0);
+              uint64_t w1 = 0ull;
+              if (two) w1 = *(const uint64_t *)(rb + g1);
+              x0 = dec_c64e(w0);
+              x1 = dec_c64e(w1);
+            } else {
+              x0 = *(const double2 *)(rb + g0);
+              if (two) x1 = *(const double2 *)(rb + g1);
+            }
+            if (v == 0) x0 = cmul(x0, s_coef[e >> nlo[v]]);
+            lds_c128 c;
+            c.x = x0.x;
+            c.y = x0.y;
+            dst[e] = c;
+            if (two) {
+              if (v == 0) x1 = cmul(x1, s_coef[e1 >> nlo[v]]);
+              c.x = x1.x;
+              c.y = x1.y;
+              dst[e1] = c;
+            }
+          }
+        };
+        auto rowmap = [&](uint32_t jj) __attribute__((always_inline)) {
+          const uint32_t lo4 = jj & 15u;
+          return u * jspan + ((jj & ~15u) | (((lo4 >> 0) & 1u) << (rord & 3u)) |
+                              (((lo4 >> 1) & 1u) << ((rord >> 2) & 3u)) |
+                              (((lo4 >> 2) & 1u) << ((rord >> 4) & 3u)) |
+                              (((lo4 >> 3) & 1u) << ((rord >> 6) & 3u)));
+        };
+#pragma unroll 1
+        for (uint32_t jj = 0; jj < jspan; jj += 2) {
+          // rows 2i and 2i+1 of the visiting order differ in row bit rord & 3
+          const uint32_t row0 = rowmap(jj), row1 = rowmap(jj + 1);
+          if ((jj & 15u) == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+              cbase[v] = (const char *)d.in[v].base +
+                         (I.off[v] + ((uint64_t)dpext(row0 >> 4, hmask[v]) << hshift[v])) * (v < NF ? 8u : 16u);
+          }
+          __syncthreads();  // the previous rows' readers are done
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const uint32_t kv = row0 & rdep[v];
+            if (jj > 0 && kv == key[v]) continue;
+            key[v] = kv;
+            stage_op(v, row0, soff[v]);
+            if (v > 0) stage_op(v, row1, soff2[v]);
+          }
+          __syncthreads();
+          double2 acc0 = make_double2(0.0, 0.0), acc1 = make_double2(0.0, 0.0);
+          if (NV > 1 && fact) {
+            // positions 2j and 2j+1 share the last operand's element
+#pragma unroll 2
+            for (uint32_t k = 0; k < NKAP; k += 2) {
+              const double2 a0 = opnd(0, k), a1 = opnd(0, k + 1);
+              double2 h0 = a0, g0 = a1, h1 = a0, g1 = a1;
+#pragma unroll
+              for (int v = 1; v < NV - 1; ++v) {
+                h0 = cmul(h0, opnd(v, k));
+                g0 = cmul(g0, opnd(v, k + 1));
+                h1 = cmul(h1, opnd2(v, k));
+                g1 = cmul(g1, opnd2(v, k + 1));
+              }
+              acc0 = cfma(make_double2(h0.x + g0.x, h0.y + g0.y), opnd(NV - 1, k), acc0);
+              acc1 = cfma(make_double2(h1.x + g1.x, h1.y + g1.y), opnd2(NV - 1, k), acc1);
+            }
+          } else {
+#pragma unroll 2
+            for (uint32_t k = 0; k < NKAP; ++k) {
+              const double2 a = opnd(0, k);
+              double2 p0 = a, p1 = a;
+#pragma unroll
+              for (int v = 1; v < NV; ++v) {
+                p0 = cmul(p0, opnd(v, k));
+                p1 = cmul(p1, opnd2(v, k));
+              }
+              acc0 = make_double2(acc0.x + p0.x, acc0.y + p0.y);
+              acc1 = make_double2(acc1.x + p1.x, acc1.y + p1.y);
+            }
+          }
+          finish(row0, acc0);
+          finish(row1, acc1);
+        }
+        continue;
+      }
 #pragma unroll 1
       for (uint32_t jj = 0; jj < jspan; ++jj) {
         // rows of a 16-row chunk in the order rord (innermost bits first)
@@ -1366,6 +1512,15 @@ template <bool SCALE, int NK, int NV, int NF, bool FOLD>
 __global__ __launch_bounds__(256) void step_tiled(const PStep d, uint32_t nb, uint32_t ns,
                                                   uint64_t s_lo, uint32_t jspan) {
   tiled_body<SCALE, NK, NV, NF, FOLD>(d, nb, ns, s_lo, jspan, blockIdx.x, blockIdx.y, gridDim.x, gridDim.y);
+}
+
+// Row-paired form (operand 0 carries the coefficient; d.tiled_lds includes
+// the second rows' regions; jspan >= 16).
+template <bool SCALE, int NK, int NV, int NF>
+__global__ __launch_bounds__(256) void step_tiled_pair(const PStep d, uint32_t nb, uint32_t ns,
+                                                       uint64_t s_lo, uint32_t jspan) {
+  tiled_body<SCALE, NK, NV, NF, true, true>(d, nb, ns, s_lo, jspan, blockIdx.x, blockIdx.y, gridDim.x,
+                                            gridDim.y);
 }
 
 // Several independent streaming steps in one launch.  The steps of one
@@ -1654,6 +1809,7 @@ static int upload(T **dst, const std::vector<T> &src, const char *what) {
 using namespace qtn;
 
 static uint32_t tiled_lds_bytes(const PStep &d);
+static uint32_t tiled_pair_bytes(const PStep &d);
 
 // Layout and LDS sizes of a binding with S slices per wave (host only).
 struct BindShape {
@@ -1881,6 +2037,7 @@ static void fill_tables(qtn_plan_t *P, DeviceState *D, const ExecPlan &X, std::v
     d.tiled_fold = (d.nk > 0 && d.nin > d.nvary &&
                     __builtin_popcount(S_.rC >= 32 ? 0u : (d.in[0].mask >> S_.rC)) == d.nk) ? 0 : -1;
     d.tiled_lds = tiled_lds_bytes(d);
+    d.tiled_pair = tiled_pair_bytes(d);
   }
   // program blobs: LeafStage records, then PStep descriptors
   blob.clear();
@@ -2107,9 +2264,53 @@ static uint32_t tiled_lds_bytes(const PStep &d) {
   return (uint32_t)bytes;
 }
 
+// Extra LDS bytes of the row-paired form of a staged step (the second row's
+// runs of operands 1..nvary-1), or 0 when it does not apply: the step must
+// fold the coefficient into operand 0, sum at least 3 variables (the kappa
+// loop dominates) over at least two varying operands, and operand 0 must
+// lack the innermost row bit of the visiting order, so that the two rows
+// share its runs.  QTN_PAIR=0 switches it off.
+static uint32_t tiled_pair_bytes(const PStep &d) {
+  static const bool enabled = [] {
+    const char *e = std::getenv("QTN_PAIR");  // tuning switch
+    return !(e && e[0] == '0');
+  }();
+  if (!enabled || !d.tiled_lds || d.tiled_fold != 0 || d.nk < 3 || d.nvary < 2) return 0;
+  const uint32_t cb = d.rC >= 32 ? ~0u : ((1u << d.rC) - 1u);
+  const uint32_t pb = tiled_row_order(d) & 3u;
+  if ((((d.in[0].mask & cb) >> 8) >> pb) & 1u) return 0;
+  uint32_t extra = 0;
+  for (int v = 1; v < d.nvary; ++v) {
+    const OpDesc &in = d.in[v];
+    extra += (1u << (__builtin_popcount(in.mask >> d.rC) + __builtin_popcount(in.mask & cb & 255u))) * 16u;
+  }
+  if (d.tiled_lds + extra > 64 * 1024) return 0;
+  return extra;
+}
+
 template <bool SCALE, int NK, int NV>
 static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint32_t nb, uint32_t ns,
                              uint64_t s_lo, uint32_t jspan) {
+  // the row-paired form of staged steps that allow it (rows in 16-row chunks)
+  if constexpr (NK >= 3 && NV >= 2) {
+    if (d.tiled_lds && d.tiled_pair && d.tiled_fold == 0 && jspan >= 16) {
+      PStep dp = d;
+      dp.tiled_lds = d.tiled_lds + d.tiled_pair;
+      switch (d.nf32) {
+#define QTN_NFP(F)                                                                                 \
+  case F:                                                                                          \
+    if constexpr (F <= NV && (SCALE || F == 0)) {                                                  \
+      hipLaunchKernelGGL((step_tiled_pair<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256),     \
+                         dp.tiled_lds + dp.dot_lds, stream, dp, nb, ns, s_lo, jspan);              \
+      return;                                                                                      \
+    }                                                                                              \
+    break;
+        QTN_NFP(0) QTN_NFP(1) QTN_NFP(2) QTN_NFP(3) QTN_NFP(4)
+#undef QTN_NFP
+        default: break;
+      }
+    }
+  }
   // NF = number of 64-bit-form operands among the NV varying ones
   switch (d.nf32) {
 #define QTN_NF(F)                                                                                  \
@@ -2253,6 +2454,7 @@ static int launch_grid_step(const qtn_plan_t *P, const DeviceState *D, int st, h
   PStep d = D->steps[st];
   if (d.dot) d.dotp = D->blobbuf + D->dot_args_off;
   if (tu.stream_only) d.tiled_lds = 0;
+  if (!tu.pair) d.tiled_pair = 0;   // the row-paired form only where tuned in
   const uint32_t nb = sch.steps[st].bdep ? (uint32_t)B : 1;
   const uint32_t ns = sch.steps[st].sdep ? (uint32_t)cnt : 1;
   const uint64_t Q = (uint64_t)nb * ns;
@@ -2638,7 +2840,8 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
   const ExecPlan &X = P->exec[D->mode];
   const uint64_t nsl = 1ull << P->cut.size();
   const uint64_t cnt = std::min<uint64_t>(D->L.S, nsl);
-  // cache: one line per signature, "<hex signature> <target> <stream_only> <us>"
+  // cache: one line per signature, "<hex signature> <target> <variant> <us>"
+  // (variant 0 the default kernel, 1 the direct kernel, 2 the row-paired one)
   std::map<uint64_t, StepTune> cache;
   if (cache_path && cache_path[0])
     if (FILE *f = std::fopen(cache_path, "r")) {
@@ -2649,7 +2852,8 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
       while (std::fscanf(f, "%llx %u %d %lf", &sig, &target, &so, &us) == 4) {
         StepTune t;
         t.target = target;
-        t.stream_only = so != 0;
+        t.stream_only = so == 1;
+        t.pair = so == 2;
         cache[(uint64_t)sig] = t;
       }
       std::fclose(f);
@@ -2686,11 +2890,14 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
     // the state is rebuilt by the next contraction)
     double best_us = 0, default_us = 0;
     StepTune best;
+    // variants: the staged kernel (or the direct one where nothing is
+    // staged), the direct kernel, the row-paired staged kernel
     for (uint32_t target : {256u, 512u, 1024u, 2048u, 4096u})
-      for (int so = 0; so < (d.tiled_lds ? 2 : 1); ++so) {
+      for (int so = 0; so < (d.tiled_lds ? (d.tiled_pair ? 3 : 2) : 1); ++so) {
         StepTune t;
         t.target = target;
-        t.stream_only = so != 0;
+        t.stream_only = so == 1;
+        t.pair = so == 2;
         uint32_t gx = 0;
         if ((rc = launch_grid_step<SCALE>(P, D, s_, stream, 0, cnt, t, &gx))) break;
         constexpr int R = 5;
@@ -2748,7 +2955,7 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
     for (const auto &g : gain) {
       if (rc) break;
       const StepTune &c = chosen[g.second];
-      if (c.target == StepTune().target && c.stream_only == StepTune().stream_only) continue;
+      if (c.target == StepTune().target && !c.stream_only && !c.pair) continue;
       D->tune = cur;
       D->tune[g.second] = c;
       double us = 0;
@@ -2799,7 +3006,7 @@ static int autotune_impl(qtn_plan_t *P, hipStream_t stream, const char *cache_pa
     }
     for (const auto &l : learned)
       std::fprintf(f, "%016llx %u %d %.3f\n", (unsigned long long)l.first, l.second.first.target,
-                   l.second.first.stream_only ? 1 : 0, l.second.second);
+                   l.second.first.pair ? 2 : l.second.first.stream_only ? 1 : 0, l.second.second);
     std::fclose(f);
   }
   return QTN_OK;
@@ -3188,8 +3395,8 @@ extern "C" int qtn_plan_step_timing(const qtn_plan_t *P, int32_t step, qtn_kerne
   return QTN_OK;
 }
 
-extern "C" int qtn_plan_step_tune(const qtn_plan_t *P, int32_t step, uint32_t *blocks, int32_t *direct) {
-  if (!P || !P->dev || !blocks || !direct) {
+extern "C" int qtn_plan_step_tune(const qtn_plan_t *P, int32_t step, uint32_t *blocks, int32_t *variant) {
+  if (!P || !P->dev || !blocks || !variant) {
     set_error("bind a workspace first");
     return QTN_ESTATE;
   }
@@ -3199,7 +3406,7 @@ extern "C" int qtn_plan_step_tune(const qtn_plan_t *P, int32_t step, uint32_t *b
   }
   const StepTune t = P->dev->tune.empty() ? StepTune() : P->dev->tune[step];
   *blocks = t.target;
-  *direct = t.stream_only ? 1 : 0;
+  *variant = t.pair ? 2 : t.stream_only ? 1 : 0;
   return QTN_OK;
 }
 
@@ -3222,14 +3429,21 @@ extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *nam
       const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
       const std::string tf = sc ? "true" : "false";
       // the autotuner may have chosen the direct kernel for a staged step
-      const bool tiled = d.tiled_lds && !(!D->tune.empty() && D->tune[step].stream_only);
+      const StepTune tu = D->tune.empty() ? StepTune() : D->tune[step];
+      const bool tiled = d.tiled_lds && !tu.stream_only;
+      // the row-paired form runs where the step's rows come in 16-row chunks
+      uint32_t jspan = 1;
+      const uint64_t Q = (uint64_t)(P->sched.steps[step].bdep ? P->net.B : 1) *
+                         (P->sched.steps[step].sdep ? std::min<uint64_t>(D->L.S, 1ull << P->cut.size()) : 1);
+      if (streaming) (void)stream_grid(d, Q, tu.target, &jspan);
+      const bool pair = tiled && tu.pair && d.tiled_pair && d.tiled_fold == 0 && d.nk >= 3 && jspan >= 16;
       if (!streaming)
         k = "step_small<" + tf + ">";
       else
-        k = std::string(tiled ? "step_tiled<" : "step_stream<") + tf + ", " +
+        k = std::string(pair ? "step_tiled_pair<" : tiled ? "step_tiled<" : "step_stream<") + tf + ", " +
             std::to_string(d.nk) + ", " + std::to_string(d.nvary) + ", " +
             std::to_string(d.nf32 <= d.nvary ? d.nf32 : 0) +
-            (tiled ? (d.tiled_fold == 0 ? ", true>" : ", false>") : ">") +
+            (pair ? ">" : tiled ? (d.tiled_fold == 0 ? ", true>" : ", false>") : ">") +
             (d.dot ? " + closing-chain reduction" : "");
     }
   std::strncpy(name, k.c_str(), capacity - 1);

@@ -300,9 +300,9 @@ class Plan:
 
     def step_tune(self, step: int) -> dict:
         """Launch configuration in use for a grid-wide step (autotuned or default)."""
-        blocks, direct = c_uint32(0), c_int32(0)
-        _check(lib().qtn_plan_step_tune(self._h, step, byref(blocks), byref(direct)))
-        return {"blocks": blocks.value, "direct": bool(direct.value)}
+        blocks, variant = c_uint32(0), c_int32(0)
+        _check(lib().qtn_plan_step_tune(self._h, step, byref(blocks), byref(variant)))
+        return {"blocks": blocks.value, "direct": variant.value == 1, "pair": variant.value == 2}
 
     def contract_async(self, slice_lo: int, slice_hi: int, out_ptr: int,
                        stream: Optional[int] = None) -> None:

@@ -32,7 +32,7 @@ def test_autotune_keeps_results_and_caches(precision, tmp_path):
     else:
         assert st["whole_tuned_us"] == st["whole_default_us"]
     tunes = [plan.step_tune(i) for i in range(plan.info()["n_steps"])]
-    changed = [t for t in tunes if t["blocks"] != 1024 or t["direct"]]
+    changed = [t for t in tunes if t["blocks"] != 1024 or t["direct"] or t["pair"]]
     assert len(changed) == st["kept"]
     assert all(t["blocks"] in (256, 512, 1024, 2048, 4096) for t in tunes)
     after = [p.value() for p in plan.contract(0, 1, stream)]

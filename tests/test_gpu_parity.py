@@ -282,7 +282,7 @@ def test_step_timing_and_kernel_names():
     assert timed and all(per[st]["launches"] == 2 for st in timed)
     for st in timed:
         name = plan.step_kernel(st)
-        assert name.startswith(("step_stream<true", "step_tiled<true")), name
+        assert name.startswith(("step_stream<true", "step_tiled<true", "step_tiled_pair<true")), name
 
 
 @pytest.mark.parametrize("mode", ["wide", "slice"])
