@@ -381,6 +381,16 @@ int qtn_plan_step_kernel(const qtn_plan_t *plan, int32_t step, char *name, uint3
  * runs of operand 0).  Host-side; no device work. */
 int qtn_plan_step_tune(const qtn_plan_t *plan, int32_t step, uint32_t *blocks, int32_t *variant);
 
+/* Sets the launch configuration of grid-wide step `step` by hand (the same
+ * fields qtn_plan_autotune chooses; a later autotune overrides them):
+ * `blocks` in [1, 2^20] targeted over the chip, `variant` 0 default kernel,
+ * 1 direct kernel, 2 row-paired staged kernel.  A variant the step does not
+ * allow runs the default kernel; the arithmetic of every output element is
+ * unchanged (a step with the folded closing chain groups its partials by
+ * block).  Drops the captured graph.  Errors: QTN_ESTATE (no workspace),
+ * QTN_ERANGE (step), QTN_EINVAL (blocks or variant). */
+int qtn_plan_set_step_tune(qtn_plan_t *plan, int32_t step, uint32_t blocks, int32_t variant);
+
 /* ---------------------------------------------------------------------------
  * Learned cut-set cost model.  Not part of the paper: it ranks candidate cut
  * sets for the search of Sec. III B by predicted log2 cost and peak rank;

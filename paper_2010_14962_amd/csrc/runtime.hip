@@ -3410,6 +3410,29 @@ extern "C" int qtn_plan_step_tune(const qtn_plan_t *P, int32_t step, uint32_t *b
   return QTN_OK;
 }
 
+extern "C" int qtn_plan_set_step_tune(qtn_plan_t *P, int32_t step, uint32_t blocks, int32_t variant) {
+  if (!P || !P->dev) {
+    set_error("bind a workspace first");
+    return QTN_ESTATE;
+  }
+  if (step < 0 || (size_t)step >= P->sched.steps.size()) {
+    set_error("step out of range");
+    return QTN_ERANGE;
+  }
+  if (blocks < 1 || blocks > (1u << 20) || variant < 0 || variant > 2) {
+    set_error("blocks must be in [1, 2^20] and variant in {0, 1, 2}");
+    return QTN_EINVAL;
+  }
+  DeviceState *D = P->dev;
+  if (D->tune.empty()) D->tune.assign(P->sched.steps.size(), StepTune());
+  StepTune &t = D->tune[step];
+  t.target = blocks;
+  t.stream_only = variant == 1;
+  t.pair = variant == 2;
+  drop_graph(D);
+  return QTN_OK;
+}
+
 extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *name, uint32_t capacity) {
   if (!P || !P->dev || !name || capacity == 0) {
     set_error("bind a workspace first");

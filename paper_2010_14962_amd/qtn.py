@@ -99,7 +99,8 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_cost_features", "qtn_cost_exact", "qtn_mlp_create", "qtn_mlp_destroy",
            "qtn_mlp_num_params", "qtn_mlp_get_params", "qtn_mlp_set_params", "qtn_mlp_get_grads",
            "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search",
-           "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_plan_step_tune", "qtn_contract_async",
+           "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_plan_step_tune", "qtn_plan_set_step_tune",
+           "qtn_contract_async",
            "qtn_contract_ranges", "qtn_plan_fingerprint", "qtn_plan_inject_faults",
            "qtn_contract_noalloc", "qtn_batch_contract", "qtn_plan_autotune", "qtn_plan_circuit"]
 COST_FEATURES = 32
@@ -142,6 +143,7 @@ def lib():
     L.qtn_plan_step_timing.argtypes = [c_void_p, c_int32, POINTER(QtnKernelTiming)]
     L.qtn_plan_step_kernel.argtypes = [c_void_p, c_int32, c_char_p, c_uint32]
     L.qtn_plan_step_tune.argtypes = [c_void_p, c_int32, POINTER(c_uint32), POINTER(c_int32)]
+    L.qtn_plan_set_step_tune.argtypes = [c_void_p, c_int32, c_uint32, c_int32]
     L.qtn_last_error.argtypes = []
     L.qtn_last_error.restype = c_char_p
     pf, pu32 = POINTER(ctypes.c_float), POINTER(c_uint32)
@@ -303,6 +305,10 @@ class Plan:
         blocks, variant = c_uint32(0), c_int32(0)
         _check(lib().qtn_plan_step_tune(self._h, step, byref(blocks), byref(variant)))
         return {"blocks": blocks.value, "direct": variant.value == 1, "pair": variant.value == 2}
+
+    def set_step_tune(self, step: int, blocks: int = 1024, direct: bool = False, pair: bool = False):
+        """Sets a grid-wide step's launch configuration by hand."""
+        _check(lib().qtn_plan_set_step_tune(self._h, step, blocks, 2 if pair else 1 if direct else 0))
 
     def contract_async(self, slice_lo: int, slice_hi: int, out_ptr: int,
                        stream: Optional[int] = None) -> None:

@@ -185,6 +185,41 @@ def test_n80_p2_k16_slice_subset(mode):
     assert abs(a32 - a64) <= 1e-6 * abs(a64)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_row_paired_kernel(precision):
+    """The row-paired staged kernel (two rows per thread sharing operand 0's
+    staged runs), switched on by hand for every step that allows it on the
+    n=80 p=2 k=16 plan: the same amplitudes as the default kernels, and
+    single slices against the oracle."""
+    from instances import search_params
+    print("case row-paired", precision, flush=True)
+    name = "qaoa_n80_p2_k16"
+    inst = workload_instance(name, seed=0)
+    plan = plan_instance(inst, k=16, max_rank=inst.meta["max_rank"], precision=precision,
+                         **search_params(name))
+    plan.bind_torch(256)
+    ref = _amps(plan, 0, 256)[0]
+    paired = []
+    for st in range(plan.info()["n_steps"]):
+        if plan.step_kernel(st).startswith("step_tiled<"):
+            plan.set_step_tune(st, pair=True)
+            if plan.step_kernel(st).startswith("step_tiled_pair<"):
+                paired.append(st)
+            else:
+                plan.set_step_tune(st)
+    assert paired
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    got = _amps(plan, 0, 256)[0]
+    assert abs(got - ref) <= tol * abs(ref)
+    # 64 slices in one wave keep 16-row chunks in the paired steps
+    cut, order, x = plan.cut(), plan.order(), inst.bitstrings[0]
+    parts = [Q.slice_partial(80, inst.edges, 2, inst.gamma, inst.beta, x, cut, s, order=order)
+             for s in range(64)]
+    assert abs(_amps(plan, 0, 64)[0] - sum(parts)) <= tol * sum(abs(v) for v in parts)
+    with pytest.raises(qtn.QtnError):
+        plan.set_step_tune(paired[0], blocks=0)
+
+
 def test_ranges_combine_and_determinism():
     inst = workload_instance("qaoa_n40_p2_b32_k8", seed=1)
     plan = plan_instance(inst, k=8, precision="fp32")
