@@ -5,9 +5,10 @@ Workload (default): random 3-regular graph, n = 120 qubits, QAOA depth 1,
 keeps every slice tensor at rank <= 26; seeded synthetic instance.  One step
 is one contraction over all 2^k slices of all 8 bitstrings (the whole hot
 path: slice set-up, every contraction step, the FP64 slice sum, the partials
-in host memory), one synchronous qtn_contract (graph replay) per step.  The
-same steps enqueued back to back with qtn_contract_async are timed as
-well.  The mixed form (64-bit shared-exponent storage of the large tensors
+in host memory), one synchronous qtn_contract per step, in the launch mode
+(graph replay or direct launches) and per-step launch configurations that
+qtn_plan_autotune chose before the timed region.  The same steps enqueued
+back to back with qtn_contract_async are timed as well.  The mixed form (64-bit shared-exponent storage of the large tensors
 with per-instance power-of-two rescaling, FP64 arithmetic) is the headline;
 the plain FP64 GPU contraction is timed beside it.
 
