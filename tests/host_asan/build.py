@@ -1,7 +1,7 @@
-"""Builds libqtn's host code with AddressSanitizer against CPU stand-ins for
-the HIP runtime (stubs.cpp): C++ sources with g++, HIP sources host-only with
-hipcc (no device code).  Test infrastructure; the product library is built
-by paper_2010_14962_amd/build.py."""
+"""Builds libqtn's host code with AddressSanitizer (or ThreadSanitizer)
+against CPU stand-ins for the HIP runtime (stubs.cpp): C++ sources with g++,
+HIP sources host-only with hipcc (no device code).  Test infrastructure; the
+product library is built by paper_2010_14962_amd/build.py."""
 from __future__ import annotations
 
 import os
@@ -12,14 +12,9 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2010_14962_amd", "csrc")
-OUT = os.path.join(HERE, "_build")
-LIB = os.path.join(OUT, "libqtn_host_asan.so")
+
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 BASE = ["-O1", "-g", "-std=c++17", "-fPIC", "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include")]
-# host compilers take the sanitizer directly; on hipcc lines it is marked as
-# host-only (these compile no device code at all)
-GXX_SAN = ["-fsanitize=address"]
-HIPCC_SAN = ["-Xarch_host", "-fsanitize=address"]
 
 
 def _run(cmd):
@@ -29,6 +24,13 @@ def _run(cmd):
 
 
 def build() -> str:
+    """The AddressSanitizer library (for Python drivers); returns its path."""
+    OUT = os.path.join(HERE, "_build")
+    LIB = os.path.join(OUT, "libqtn_host_asan.so")
+    # host compilers take the sanitizer directly; on hipcc lines it is marked
+    # as host-only (these compile no device code at all)
+    GXX_SAN = ["-fsanitize=address"]
+    HIPCC_SAN = ["-Xarch_host", "-fsanitize=address"]
     os.makedirs(OUT, exist_ok=True)
     jobs = []
     for src in ("planner.cpp", "api.cpp", "costmodel.cpp", "ranges.cpp"):
@@ -55,6 +57,39 @@ def build() -> str:
     return LIB
 
 
+def build_threads() -> str:
+    """The host objects, the stand-ins and threads_main.cpp compiled with
+    clang and ThreadSanitizer into one executable (the sanitizer runtime
+    must be the program's own); returns its path."""
+    OUT = os.path.join(HERE, "_build_thread")
+    os.makedirs(OUT, exist_ok=True)
+    clang = "/opt/rocm/llvm/bin/clang++"
+    SAN = ["-fsanitize=thread"]
+    jobs = []
+    for src in ("planner.cpp", "api.cpp", "costmodel.cpp", "ranges.cpp"):
+        jobs.append([clang] + BASE + SAN + ["-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-c",
+                                           os.path.join(CSRC, src), "-o", os.path.join(OUT, src + ".o")])
+    for src in ("runtime.hip", "mlp.hip"):
+        jobs.append([HIPCC, "--offload-arch=gfx950", "--cuda-host-only"] + BASE + ["-Xarch_host", "-fsanitize=thread"] +
+                    ["-c", os.path.join(CSRC, src), "-o", os.path.join(OUT, src + ".o")])
+    for src in ("stubs.cpp", "threads_main.cpp"):
+        jobs.append([clang] + BASE + SAN + ["-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-c",
+                                           os.path.join(HERE, src), "-o", os.path.join(OUT, src + ".o")])
+    with ThreadPoolExecutor(min(len(jobs), 8)) as ex:
+        list(ex.map(_run, jobs))
+    objs = [os.path.join(OUT, f) for f in sorted(os.listdir(OUT)) if f.endswith(".o") and f != "fatbin.o"]
+    nm = subprocess.run(["nm", "-u"] + objs, capture_output=True, text=True).stdout
+    names = sorted({l.split()[-1] for l in nm.splitlines() if "__hip_fatbin_" in l})
+    fat_c = os.path.join(OUT, "fatbin.c")
+    with open(fat_c, "w") as f:
+        for n in names:
+            f.write("char %s[64];\n" % n)
+    _run(["gcc", "-fPIC", "-c", fat_c, "-o", os.path.join(OUT, "fatbin.o")])
+    exe = os.path.join(OUT, "threads_main")
+    _run([clang, "-fsanitize=thread", "-o", exe] + objs + [os.path.join(OUT, "fatbin.o"), "-lpthread"])
+    return exe
+
+
 if __name__ == "__main__":
-    print(build())
+    print(build_threads() if sys.argv[1:] == ["thread"] else build())
     sys.exit(0)

@@ -1,8 +1,9 @@
-"""libqtn's host code under AddressSanitizer, on the CPU: the planner, the
-workspace layout, the launch logic, the autotuner, ranges with checkpoints,
-the no-allocation and batched entry points, general circuits and the
-density-matrix form, driven through the C ABI with the HIP runtime replaced
-by CPU stand-ins (tests/host_asan).  No device code runs."""
+"""libqtn's host code under AddressSanitizer and ThreadSanitizer, on the
+CPU: the planner, the workspace layout, the launch logic, the autotuner,
+ranges with checkpoints, the no-allocation and batched entry points, general
+circuits and the density-matrix form, driven through the C ABI with the HIP
+runtime replaced by CPU stand-ins (tests/host_asan); and the thread pool of
+the exact cost evaluation.  No device code runs."""
 import os
 import shutil
 import subprocess
@@ -40,3 +41,23 @@ def test_host_code_under_address_sanitizer():
     assert "AddressSanitizer" not in out, out[-4000:]
     assert r.returncode == 0, out[-4000:]
     assert out.rstrip().endswith("done") or "\ndone" in out, out[-2000:]
+
+
+def _load_build():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("qtn_host_asan_build", os.path.join(ASAN_DIR, "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_thread_pool_under_thread_sanitizer():
+    if not os.path.isdir(ASAN_DIR):
+        pytest.skip("host sanitizer harness not present")
+    if not os.path.exists("/opt/rocm/llvm/bin/clang++") or not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("clang++ or hipcc not available")
+    exe = _load_build().build_threads()
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    out = r.stdout + r.stderr
+    assert "ThreadSanitizer" not in out, out[-4000:]
+    assert r.returncode == 0 and "done" in out, out[-4000:]
