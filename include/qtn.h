@@ -55,10 +55,11 @@ enum {
  * 8-bit exponent shared by the real and imaginary parts and two 28-bit
  * two's-complement mantissas (absolute error at most 2^-28 |z| per part,
  * against 2^-24 of each part for complex64), with a per-instance power-of-two
- * exponent (rescaled after every grid-wide step); small tensors (under 3% of
- * the bytes), LDS-resident program tensors and the gate factors stay
- * complex128; all products and sums run in FP64 registers.  The slice sum is
- * always FP64.
+ * exponent (rescaled after every grid-wide step, or not at all in
+ * synchronous calls whose values stay in range: qtn_plan_range_state); small
+ * tensors (under 3% of the bytes), LDS-resident program tensors and the gate
+ * factors stay complex128; all products and sums run in FP64 registers.  The
+ * slice sum is always FP64.
  */
 enum { QTN_FP64 = 0, QTN_FP32 = 1, QTN_3XBF16 = 2 };
 
@@ -380,6 +381,22 @@ int qtn_plan_step_kernel(const qtn_plan_t *plan, int32_t step, char *name, uint3
  * row-paired staged kernel (each thread sums two rows that share the staged
  * runs of operand 0).  Host-side; no device work. */
 int qtn_plan_step_tune(const qtn_plan_t *plan, int32_t step, uint32_t *blocks, int32_t *variant);
+
+/* Rescaling of the mixed form (QTN_FP32, above; not part of the paper's
+ * method, which does not fix a precision).  For callers that want to know
+ * which kernels ran; no caller has to act on it.  A plan that
+ * stores tensors in the 64-bit form runs synchronous qtn_contract calls
+ * without per-instance rescaling while the values stay inside the form's
+ * exponent range: every encoder that would flush a non-zero value below
+ * 2^-127 or clamp one at 2^128 sets a device word, the call's last kernel
+ * hands it to the host, and a call that set it is repeated with rescaling
+ * (the returned partials are those of the rescaled run).  After two such
+ * calls in a row, or with QTN_RESCALE=1 in the environment at bind time,
+ * every call rescales.  Asynchronous calls, qtn_contract_noalloc and
+ * qtn_batch_contract always rescale.  *unscaled = 1 while synchronous calls
+ * run without rescaling; *reruns = calls repeated so far.  Errors:
+ * QTN_ESTATE (no workspace). */
+int qtn_plan_range_state(const qtn_plan_t *plan, int32_t *unscaled, uint64_t *reruns);
 
 /* Sets the launch configuration of grid-wide step `step` by hand (the same
  * fields qtn_plan_autotune chooses; a later autotune overrides them):

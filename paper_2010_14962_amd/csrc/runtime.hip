@@ -194,6 +194,16 @@ struct DeviceState {
   hipGraphExec_t gexec = nullptr;
   uint64_t g_lo = 0, g_hi = 0;
   bool g_timing = false;
+  bool g_scaled = false;
+  // plans that store tensors in the 64-bit form: synchronous contractions
+  // run without per-instance rescaling (the values are checked against the
+  // form's exponent range by qtn_range_flag) until one leaves the range;
+  // from then on, and for asynchronous calls, they rescale
+  bool unscaled = true;
+  bool force_scaled = false;      // the re-run of a contraction that left the range
+  int range_misses = 0;           // consecutive such contractions
+  uint64_t range_reruns = 0;      // contractions repeated with rescaling
+  uint32_t *flag_dev = nullptr;   // device address of the range word (host_partials slot B)
   size_t g_ev_used = 0;
   std::vector<double> g_ev_bytes, g_ev_flops;
   std::vector<int> g_ev_step;
@@ -260,12 +270,19 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
 // rounded to the nearest multiple of 2^(e-27): an absolute error of at most
 // 2^-28 |z| per part (complex64 rounds each part to 2^-24 of itself).  The
 // same eight bytes as complex64.
+// Set (on the device that ran it) when enc_c64e flushed a non-zero value or
+// clamped one: in a run without per-instance rescaling that means the values
+// left the 64-bit form's exponent range and the contraction is repeated with
+// rescaling.  Read and cleared by the last slice_sum of each contraction.
+__device__ uint32_t qtn_range_flag;
+
 __device__ __forceinline__ uint64_t enc_c64e(double2 v) {
   const double m = fmax(fabs(v.x), fabs(v.y));
   if (!(m > 0.0)) return 0ull;
   int e;
   (void)frexp(m, &e);
   const int E = e + 127;
+  if (E < 1 || E > 255) atomicOr(&qtn_range_flag, 1u);
   if (E < 1) return 0ull;   // below 2^-127 of the instance scale: flushed
   const double lim = 134217727.0;  // 2^27 - 1
   const int sh = 27 - min(e, 128);
@@ -1570,7 +1587,7 @@ __global__ __launch_bounds__(256) void step_multi(const MultiArgs args) {
   switch (a.vid[m]) {
 #define QTN_MULTI_CASE(T, K, V, F)                                                                 \
   case ((T * 2 + K - 1) * 2 + V - 2) * 2 + F:                                                      \
-    if constexpr (SCALE || F == 0) {                                                               \
+    if constexpr (true) {                                                               \
       if constexpr (T)                                                                             \
         tiled_body<SCALE, K, V, F, true>(d, a.nb[m], a.ns[m], a.s_lo, a.jspan[m], bx, by, gx, gy); \
       else                                                                                         \
@@ -1637,7 +1654,8 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
                                                  qtn_partial *partials, int init,
                                                  qtn_partial *host_out, uint32_t *clear,
                                                  uint64_t nclear, uint64_t keep_lo, uint64_t keep_hi,
-                                                 const double2 *dotp, uint64_t dstride, uint32_t dslots) {
+                                                 const double2 *dotp, uint64_t dstride, uint32_t dslots,
+                                                 uint32_t *flag_out) {
   __shared__ double sre[256], cre[256], sim[256], cim[256];
   const uint32_t b = blockIdx.x;
   const uint32_t t = threadIdx.x;
@@ -1738,8 +1756,16 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
       partials[b] = a;
       w = a;
     }
-    // the last wave also writes the result straight to pinned host memory
-    if (host_out) host_out[b] = w;
+    // the last wave also writes the result straight to its destination;
+    // block 0 takes the range flag of the whole contraction (to flag_out when
+    // given) and clears it for the next one (every earlier kernel has ended)
+    if (host_out) {
+      host_out[b] = w;
+      if (b == 0) {
+        const uint32_t f = atomicExch(&qtn_range_flag, 0u);
+        if (flag_out) *flag_out = f;
+      }
+    }
   }
   // Clear the exponent words for the next wave, except the result's
   // exponents [keep_lo, keep_hi) that this kernel reads; every other word
@@ -2184,9 +2210,15 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
     if (int rc = upload(&lb, host, "hipMalloc(leaves)")) return rc;
     D->leafbuf = lb;
     // pinned host memory the slice sum writes the final partials to
-    HIP_TRY(hipHostMalloc((void **)&D->host_partials, std::max<uint64_t>(P->net.B, 1) * sizeof(qtn_partial),
+    HIP_TRY(hipHostMalloc((void **)&D->host_partials, (P->net.B + 1) * sizeof(qtn_partial),
                           hipHostMallocMapped));
     HIP_TRY(hipHostGetDevicePointer((void **)&D->host_partials_dev, D->host_partials, 0));
+    D->flag_dev = (uint32_t *)(D->host_partials_dev + P->net.B);
+    static const bool rescale_always = [] {
+      const char *e = std::getenv("QTN_RESCALE");  // tuning switch: 1 rescales every contraction
+      return e && e[0] == '1';
+    }();
+    D->unscaled = !rescale_always;
   }
   if (int rc = set_program_lds(lds_total)) return rc;
   LaunchGraph lg;
@@ -2299,7 +2331,7 @@ static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint
       switch (d.nf32) {
 #define QTN_NFP(F)                                                                                 \
   case F:                                                                                          \
-    if constexpr (F <= NV && (SCALE || F == 0)) {                                                  \
+    if constexpr (F <= NV) {                                                  \
       hipLaunchKernelGGL((step_tiled_pair<SCALE, NK, NV, (F <= NV ? F : 0)>), grid, dim3(256),     \
                          dp.tiled_lds + dp.dot_lds, stream, dp, nb, ns, s_lo, jspan);              \
       return;                                                                                      \
@@ -2315,7 +2347,7 @@ static void launch_stream_nv(const PStep &d, dim3 grid, hipStream_t stream, uint
   switch (d.nf32) {
 #define QTN_NF(F)                                                                                  \
   case F:                                                                                          \
-    if constexpr (F <= NV && (SCALE || F == 0)) /* FP64 plans store nothing in 8 bytes */        \
+    if constexpr (F <= NV)        \
     {                                                                                              \
       if (d.tiled_lds && d.tiled_fold == 0)                                                        \
         hipLaunchKernelGGL((step_tiled<SCALE, NK, NV, (F <= NV ? F : 0), true>), grid, dim3(256),  \
@@ -2377,7 +2409,6 @@ static int multi_shape(const PStep &d, bool scale, bool stream_only) {
   if (tiled && d.tiled_fold != 0) return -1;
   if (d.nk < 1 || d.nk > 2 || d.nvary < 2 || d.nvary > 3 || d.nf32 > 1) return -1;
   if (!tiled && (d.nk != 1 || d.nvary != 2)) return -1;
-  if (!scale && d.nf32) return -1;
   return (((tiled ? 1 : 0) * 2 + d.nk - 1) * 2 + d.nvary - 2) * 2 + d.nf32;
 }
 
@@ -2519,7 +2550,8 @@ static int run_waves(qtn_plan_t *P, DeviceState *D, uint64_t lo, uint64_t hi, hi
                            D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
                            SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0,
                            folded ? (const double2 *)(D->ws + D->L.dot_off) : (const double2 *)nullptr,
-                           (uint64_t)D->L.dot_slots, dot_gx);
+                           (uint64_t)D->L.dot_slots, dot_gx,
+                           s_lo + S >= hi ? D->flag_dev : (uint32_t *)nullptr);
         first = false;
       } else {
         const size_t g = (size_t)(u - 1);
@@ -2656,6 +2688,16 @@ static int run_waves(qtn_plan_t *P, DeviceState *D, uint64_t lo, uint64_t hi, hi
   return QTN_OK;
 }
 
+// Whether a contraction of this plan runs the rescaling kernels: plans that
+// store tensors in the 64-bit form rescale in asynchronous calls (whose
+// results cannot be checked before they are used), in the re-run of a
+// synchronous call that left the form's exponent range, and once that has
+// happened twice in a row; otherwise synchronous calls run without
+// rescaling (qtn_range_flag guards them).
+static bool scaled_run(const qtn_plan_t *P, const DeviceState *D, bool async) {
+  return P->scaled[D->mode] && (async || !D->unscaled || D->force_scaled);
+}
+
 static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v,
                          qtn_partial *out, bool async) {
   set_error("");
@@ -2703,9 +2745,9 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
       D->ev.push_back(e);
     }
   }
+  const bool sc = scaled_run(P, D, async);
   auto enqueue = [&](hipStream_t st, bool concurrent) {
-    return !P->scaled[D->mode] ? run_waves<false>(P, D, lo, hi, st, concurrent)
-                                    : run_waves<true>(P, D, lo, hi, st, concurrent);
+    return !sc ? run_waves<false>(P, D, lo, hi, st, concurrent) : run_waves<true>(P, D, lo, hi, st, concurrent);
   };
   if (D->use_graphs) {
     // The launch sequence of [lo, hi) is captured once on an internal stream
@@ -2713,7 +2755,7 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
     if (!D->gstream) {
       HIP_TRY(hipStreamCreateWithFlags(&D->gstream, hipStreamNonBlocking));
     }
-    if (!D->gexec || D->g_lo != lo || D->g_hi != hi || D->g_timing != D->timing) {
+    if (!D->gexec || D->g_lo != lo || D->g_hi != hi || D->g_timing != D->timing || D->g_scaled != sc) {
       drop_graph(D);
       D->ev_used = 0;
       D->ev_bytes.clear();
@@ -2737,6 +2779,7 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
       D->g_lo = lo;
       D->g_hi = hi;
       D->g_timing = D->timing;
+      D->g_scaled = sc;
       D->g_ev_used = D->ev_used;
       D->g_ev_bytes = D->ev_bytes;
       D->g_ev_flops = D->ev_flops;
@@ -2801,6 +2844,32 @@ static int contract_impl(qtn_plan_t *P, uint64_t lo, uint64_t hi, void *stream_v
   D->ev_bytes.clear();
   D->ev_flops.clear();
   D->ev_step.clear();
+  if (!async && P->scaled[D->mode] && !sc) {
+    // a run without rescaling: repeat it with rescaling if any value left
+    // the 64-bit form's exponent range (QTN_RANGE_TEST=1, a test hook, makes
+    // every such run count as one that did)
+    const char *tf = std::getenv("QTN_RANGE_TEST");
+    const bool miss = *(volatile uint32_t *)(D->host_partials + B) != 0u || (tf && tf[0] == '1');
+    if (miss) {
+      if (++D->range_misses >= 2) D->unscaled = false;
+      ++D->range_reruns;
+      D->force_scaled = true;
+      const int rc = contract_impl(P, lo, hi, stream_v, out, false);
+      D->force_scaled = false;
+      return rc;
+    }
+    D->range_misses = 0;
+  }
+  return QTN_OK;
+}
+
+extern "C" int qtn_plan_range_state(const qtn_plan_t *P, int32_t *unscaled, uint64_t *reruns) {
+  if (!P || !P->dev || !unscaled || !reruns) {
+    set_error("bind a workspace first");
+    return QTN_ESTATE;
+  }
+  *unscaled = (P->scaled[P->dev->mode] && P->dev->unscaled) ? 1 : 0;
+  *reruns = P->dev->range_reruns;
   return QTN_OK;
 }
 
@@ -3028,8 +3097,8 @@ extern "C" int qtn_plan_autotune(qtn_plan_t *P, void *stream_v, const char *cach
   }
   std::memset(stats, 0, sizeof(*stats));
   const hipStream_t stream = (hipStream_t)stream_v;
-  return !P->scaled[P->dev->mode] ? autotune_impl<false>(P, stream, cache_path, stats)
-                                  : autotune_impl<true>(P, stream, cache_path, stats);
+  return !scaled_run(P, P->dev, false) ? autotune_impl<false>(P, stream, cache_path, stats)
+                                       : autotune_impl<true>(P, stream, cache_path, stats);
 }
 
 // ---------------------------------------------------------------------------
@@ -3105,7 +3174,7 @@ static int batch_enqueue(qtn_plan_t *const *plans, uint32_t n, const uint64_t *l
                        (SCALE && D->L.exp_bytes) ? (uint32_t *)(D->ws + D->L.data_bytes) : (uint32_t *)nullptr,
                        D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
                        SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0,
-                       (const double2 *)nullptr, (uint64_t)0, 0u);
+                       (const double2 *)nullptr, (uint64_t)0, 0u, (uint32_t *)nullptr);
   }
   HIP_TRY(hipGetLastError());
   return QTN_OK;
@@ -3448,7 +3517,7 @@ extern "C" int qtn_plan_step_kernel(const qtn_plan_t *P, int32_t step, char *nam
   for (const LaunchGroup &G : X.launches)
     if (G.kind == 1 && G.step == step) {
       const PStep &d = D->steps[step];
-      const bool sc = P->scaled[D->mode];
+      const bool sc = scaled_run(P, D, false);   // the kernels a synchronous call runs
       const bool streaming = d.rC >= kStreamMinRank && d.nk <= 4 && d.nvary >= 1 && d.nvary <= 4;
       const std::string tf = sc ? "true" : "false";
       // the autotuner may have chosen the direct kernel for a staged step

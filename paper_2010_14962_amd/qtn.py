@@ -100,6 +100,7 @@ EXPORTS = ["qtn_plan_opts_default", "qtn_plan", "qtn_plan_destroy", "qtn_plan_qu
            "qtn_mlp_num_params", "qtn_mlp_get_params", "qtn_mlp_set_params", "qtn_mlp_get_grads",
            "qtn_mlp_set_normalization", "qtn_mlp_forward", "qtn_mlp_train_step", "qtn_cut_search",
            "qtn_plan_step_timing", "qtn_plan_step_kernel", "qtn_plan_step_tune", "qtn_plan_set_step_tune",
+           "qtn_plan_range_state",
            "qtn_contract_async",
            "qtn_contract_ranges", "qtn_plan_fingerprint", "qtn_plan_inject_faults",
            "qtn_contract_noalloc", "qtn_batch_contract", "qtn_plan_autotune", "qtn_plan_circuit"]
@@ -144,6 +145,7 @@ def lib():
     L.qtn_plan_step_kernel.argtypes = [c_void_p, c_int32, c_char_p, c_uint32]
     L.qtn_plan_step_tune.argtypes = [c_void_p, c_int32, POINTER(c_uint32), POINTER(c_int32)]
     L.qtn_plan_set_step_tune.argtypes = [c_void_p, c_int32, c_uint32, c_int32]
+    L.qtn_plan_range_state.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_uint64)]
     L.qtn_last_error.argtypes = []
     L.qtn_last_error.restype = c_char_p
     pf, pu32 = POINTER(ctypes.c_float), POINTER(c_uint32)
@@ -305,6 +307,13 @@ class Plan:
         blocks, variant = c_uint32(0), c_int32(0)
         _check(lib().qtn_plan_step_tune(self._h, step, byref(blocks), byref(variant)))
         return {"blocks": blocks.value, "direct": variant.value == 1, "pair": variant.value == 2}
+
+    def range_state(self) -> dict:
+        """Whether synchronous contractions run without rescaling, and how
+        many were repeated with rescaling after leaving the 64-bit range."""
+        u, r = c_int32(0), c_uint64(0)
+        _check(lib().qtn_plan_range_state(self._h, byref(u), byref(r)))
+        return {"unscaled": bool(u.value), "reruns": r.value}
 
     def set_step_tune(self, step: int, blocks: int = 1024, direct: bool = False, pair: bool = False):
         """Sets a grid-wide step's launch configuration by hand."""

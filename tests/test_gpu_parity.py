@@ -8,6 +8,7 @@ when |r| < 1e-6 * 2^{-n/2} (a near-cancelling amplitude) the denominator is
 slice value of the same bitstring.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -220,6 +221,55 @@ def test_row_paired_kernel(precision):
         plan.set_step_tune(paired[0], blocks=0)
 
 
+def test_mixed_form_without_rescaling_and_range_fallback():
+    """Synchronous contractions of a plan with 64-bit-form tensors run
+    without per-instance rescaling while the values stay in the form's
+    exponent range (the same bits as the rescaled asynchronous run), and a
+    run whose values leave it is repeated with rescaling (a general circuit
+    whose single-qubit gates are scaled by 1/4, so that late tensors fall
+    below 2^-127), against the statevector."""
+    from instances.circuits import random_circuit
+    from oracle import circuits as OC
+    print("case unrescaled mixed form", flush=True)
+    c = random_circuit(14, 12, 2, 0)
+    plan = qtn.qtn_plan_circuit(c.n, c.gates, c.bitstrings, k=0, precision="fp32")
+    assert plan.info()["rescaled"] & 1
+    plan.bind_torch(1)
+    sync = _amps(plan, 0, 1)
+    assert plan.range_state() == {"unscaled": True, "reruns": 0}
+    buf = torch.zeros((2, 4), dtype=torch.float64).pin_memory()
+    plan.contract_async(0, 1, buf.data_ptr(), _stream())
+    torch.cuda.synchronize()
+    asyn = [complex(r[0] + r[2], r[1] + r[3]) for r in buf.numpy()]
+    for b in range(2):
+        ref = OC.amplitude_statevector(c.n, c.gates, c.bitstrings[b])
+        assert abs(sync[b] - asyn[b]) <= 1e-12 * abs(asyn[b])
+        assert abs(sync[b] - ref) <= 1e-6 * abs(ref)
+    # the host-forced hook: a run counted as out of range is repeated
+    os.environ["QTN_RANGE_TEST"] = "1"
+    try:
+        again = _amps(plan, 0, 1)
+    finally:
+        del os.environ["QTN_RANGE_TEST"]
+    assert plan.range_state() == {"unscaled": True, "reruns": 1}
+    assert all(abs(a - b) <= 1e-12 * abs(b) for a, b in zip(again, asyn))
+    plan.close()
+    # values that really leave the range
+    small = [(qs, np.asarray(U) * 0.25 if len(qs) == 1 else U) for qs, U in c.gates]
+    plan = qtn.qtn_plan_circuit(c.n, small, c.bitstrings, k=0, precision="fp32")
+    plan.bind_torch(1)
+    refs = [OC.amplitude_statevector(c.n, small, c.bitstrings[b]) for b in range(2)]
+    assert 0 < abs(refs[0]) < 2.0 ** -150
+    for call in range(3):
+        got = _amps(plan, 0, 1)
+        for b in range(2):
+            assert abs(got[b] - refs[b]) <= 1e-6 * abs(refs[b])
+        st = plan.range_state()
+        # two misses in a row make every later call rescale from the start
+        assert st == {"unscaled": call == 0, "reruns": min(call + 1, 2)}, (call, st)
+    plan.close()
+
+
 def test_ranges_combine_and_determinism():
     inst = workload_instance("qaoa_n40_p2_b32_k8", seed=1)
     plan = plan_instance(inst, k=8, precision="fp32")
@@ -315,9 +365,12 @@ def test_step_timing_and_kernel_names():
     assert abs(sum(p["total_ms"] for p in per) - total["total_ms"]) <= 1e-9 * max(1.0, total["total_ms"])
     timed = [st for st, p in enumerate(per) if p["launches"]]
     assert timed and all(per[st]["launches"] == 2 for st in timed)
+    # synchronous calls of this mixed plan run without rescaling while the
+    # values stay in the 64-bit form's range
+    tf = "false" if plan.range_state()["unscaled"] else "true"
     for st in timed:
         name = plan.step_kernel(st)
-        assert name.startswith(("step_stream<true", "step_tiled<true", "step_tiled_pair<true")), name
+        assert name.startswith(tuple("%s<%s" % (k, tf) for k in ("step_stream", "step_tiled", "step_tiled_pair"))), name
 
 
 @pytest.mark.parametrize("mode", ["wide", "slice"])
