@@ -241,7 +241,10 @@ def sliced_row(name, seed, slices_per_wave, reps, with_cpu, autotune=True):
                     "ms_per_step": 1e3 * el / reps,
                     # 1: some intermediate in the 64-bit form, rescaling kernels;
                     # 0: every tensor complex128, the FP64 kernels
-                    "rescaled": int(plan.info()["rescaled"]), "autotune": tune}
+                    "rescaled": int(plan.info()["rescaled"]), "autotune": tune,
+                    # synchronous calls without rescaling, and calls repeated
+                    # with rescaling after leaving the 64-bit range
+                    "range": plan.range_state()}
         print("# %s %s: %.1f ms per contraction of %d slice instances" %
               (name, tag, 1e3 * el / reps, B * nsl), file=sys.stderr, flush=True)
         if tag == "mixed":
@@ -474,9 +477,12 @@ def main():
                    "seed": args.seed, "slices_per_wave": S, "graph": "random 3-regular",
                    "rescaled": int(info["rescaled"]),
                    "precision": "mixed: large tensors stored in 8 bytes (shared 8-bit exponent, "
-                                "two 28-bit mantissas) with per-instance power-of-two rescaling, "
+                                "two 28-bit mantissas); synchronous calls without rescaling while "
+                                "every value stays in the form's exponent range (else repeated with "
+                                "per-instance power-of-two rescaling), asynchronous calls rescaled; "
                                 "fp64 arithmetic, fp64 compensated slice sum"},
         "slices_per_sec": slices_per_s,
+        "range": mixed.range_state(),
         "timing": "one synchronous qtn_contract per step (%s, partials in host memory)" %
                   ("graph replay" if bench_graphs(mixed) else "direct launches"),
         "autotune": tune,
