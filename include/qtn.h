@@ -394,7 +394,8 @@ int qtn_plan_step_tune(const qtn_plan_t *plan, int32_t step, uint32_t *blocks, i
  * calls in a row, or with QTN_RESCALE=1 in the environment at bind time,
  * every call rescales.  Asynchronous calls, qtn_contract_noalloc and
  * qtn_batch_contract always rescale.  *unscaled = 1 while synchronous calls
- * run without rescaling; *reruns = calls repeated so far.  Errors:
+ * run without the rescaling kernels (always for plans that store nothing in
+ * the 64-bit form); *reruns = calls repeated so far.  Errors:
  * QTN_ESTATE (no workspace). */
 int qtn_plan_range_state(const qtn_plan_t *plan, int32_t *unscaled, uint64_t *reruns);
 

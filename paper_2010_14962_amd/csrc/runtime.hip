@@ -2868,7 +2868,7 @@ extern "C" int qtn_plan_range_state(const qtn_plan_t *P, int32_t *unscaled, uint
     set_error("bind a workspace first");
     return QTN_ESTATE;
   }
-  *unscaled = (P->scaled[P->dev->mode] && P->dev->unscaled) ? 1 : 0;
+  *unscaled = scaled_run(P, P->dev, false) ? 0 : 1;
   *reruns = P->dev->range_reruns;
   return QTN_OK;
 }
