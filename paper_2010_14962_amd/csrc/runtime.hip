@@ -282,7 +282,10 @@ __device__ __forceinline__ uint64_t enc_c64e(double2 v) {
   int e;
   (void)frexp(m, &e);
   const int E = e + 127;
-  if (E < 1 || E > 255) atomicOr(&qtn_range_flag, 1u);
+  // one atomic per wave and store, from its lowest lane that left the range
+  const bool out = E < 1 || E > 255;
+  const uint64_t outs = __ballot(out);
+  if (out && __lane_id() == (uint32_t)(__ffsll((unsigned long long)outs) - 1)) atomicOr(&qtn_range_flag, 1u);
   if (E < 1) return 0ull;   // below 2^-127 of the instance scale: flushed
   const double lim = 134217727.0;  // 2^27 - 1
   const int sh = 27 - min(e, 128);
