@@ -388,8 +388,9 @@ int qtn_plan_step_tune(const qtn_plan_t *plan, int32_t step, uint32_t *blocks, i
  * stores tensors in the 64-bit form runs synchronous qtn_contract calls
  * without per-instance rescaling while the values stay inside the form's
  * exponent range: every encoder that would flush a non-zero value below
- * 2^-127 or clamp one at 2^128 sets a device word, the call's last kernel
- * hands it to the host, and a call that set it is repeated with rescaling
+ * 2^-127 or clamp one at 2^128 sets a word of the plan's workspace, the
+ * call's last kernel hands it to the host, and a call that set it is
+ * repeated with rescaling
  * (the returned partials are those of the rescaled run).  After two such
  * calls in a row, or with QTN_RESCALE=1 in the environment at bind time,
  * every call rescales.  Asynchronous calls, qtn_contract_noalloc and

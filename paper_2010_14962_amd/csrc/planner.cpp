@@ -1067,7 +1067,8 @@ Layout layout(Schedule &s, const ExecPlan &x, uint64_t B, uint64_t S, uint64_t w
   }
   L.exp_bytes = eo - L.data_bytes;
   L.partial_off = eo;
-  uint64_t po = align256(eo + B * 32);
+  L.flag_off = eo + B * 32;
+  uint64_t po = align256(eo + B * 32 + 4);
   if (x.dot_step >= 0) {
     const Tensor &T = s.tensors[x.dot_tensor];
     L.dot_slots = (uint64_t)1 << std::max(0, s.steps[x.dot_step].rC - 8);

@@ -228,6 +228,7 @@ struct Layout {
   uint64_t exp_bytes = 0;        // exponents region
   uint64_t total_bytes = 0;
   uint64_t partial_off = 0;      // running per-bitstring partials
+  uint64_t flag_off = 0;         // range word of the 64-bit form (after the partials)
   uint64_t scratch_off = 0;      // per-workgroup scratch region
   uint64_t wg_slots = 0;
   uint64_t dot_off = 0;          // block partials of a folded closing chain

@@ -64,7 +64,7 @@ struct PStep {
                           //    gate factors (DotArgs) instead of storing them
   uint32_t dot_lds;       // dynamic LDS bytes of that epilogue
   const void *dotp;       // DotArgs in device memory (set at launch)
-  uint32_t pad_[2];       // size a multiple of 16 bytes
+  uint32_t *range_flag;   // the workspace's range word (enc_c64e)
 };
 static_assert(sizeof(PStep) % 16 == 0, "PStep layout");
 
@@ -197,7 +197,7 @@ struct DeviceState {
   bool g_scaled = false;
   // plans that store tensors in the 64-bit form: synchronous contractions
   // run without per-instance rescaling (the values are checked against the
-  // form's exponent range by qtn_range_flag) until one leaves the range;
+  // form's exponent range by the range word) until one leaves the range;
   // from then on, and for asynchronous calls, they rescale
   bool unscaled = true;
   bool force_scaled = false;      // the re-run of a contraction that left the range
@@ -270,13 +270,12 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
 // rounded to the nearest multiple of 2^(e-27): an absolute error of at most
 // 2^-28 |z| per part (complex64 rounds each part to 2^-24 of itself).  The
 // same eight bytes as complex64.
-// Set (on the device that ran it) when enc_c64e flushed a non-zero value or
-// clamped one: in a run without per-instance rescaling that means the values
-// left the 64-bit form's exponent range and the contraction is repeated with
-// rescaling.  Read and cleared by the last slice_sum of each contraction.
-__device__ uint32_t qtn_range_flag;
-
-__device__ __forceinline__ uint64_t enc_c64e(double2 v) {
+// The range word `flag` (one per plan workspace) is set when enc_c64e
+// flushes a non-zero value or clamps one: in a run without per-instance
+// rescaling that means the values left the 64-bit form's exponent range and
+// the contraction is repeated with rescaling.  Read and cleared by the last
+// slice_sum of each contraction.
+__device__ __forceinline__ uint64_t enc_c64e(double2 v, uint32_t *flag) {
   const double m = fmax(fabs(v.x), fabs(v.y));
   if (!(m > 0.0)) return 0ull;
   int e;
@@ -285,7 +284,7 @@ __device__ __forceinline__ uint64_t enc_c64e(double2 v) {
   // one atomic per wave and store, from its lowest lane that left the range
   const bool out = E < 1 || E > 255;
   const uint64_t outs = __ballot(out);
-  if (out && __lane_id() == (uint32_t)(__ffsll((unsigned long long)outs) - 1)) atomicOr(&qtn_range_flag, 1u);
+  if (out && flag && __lane_id() == (uint32_t)(__ffsll((unsigned long long)outs) - 1)) atomicOr(flag, 1u);
   if (E < 1) return 0ull;   // below 2^-127 of the instance scale: flushed
   const double lim = 134217727.0;  // 2^27 - 1
   const int sh = 27 - min(e, 128);
@@ -342,11 +341,11 @@ __device__ __forceinline__ double2 load_g(const void *base, uint32_t f64, uint64
   return dec_c64e(((const uint64_t *)base)[i]);
 }
 
-__device__ __forceinline__ void store_g(void *base, uint32_t f64, uint64_t i, double2 v) {
+__device__ __forceinline__ void store_g(void *base, uint32_t f64, uint64_t i, double2 v, uint32_t *flag) {
   if (f64)
     ((double2 *)base)[i] = v;
   else
-    ((uint64_t *)base)[i] = enc_c64e(v);
+    ((uint64_t *)base)[i] = enc_c64e(v, flag);
 }
 
 // Exponent e with 2^(e-1) <= x < 2^e for the positive float with bits `b`
@@ -659,7 +658,7 @@ __device__ void wg_step_n(const QTN_LDS PStep &st, uint32_t b, uint32_t sl, uint
     if (oloc == LOC_LDS)
       lds_st(W.lds, ooff / 16 + c, v);
     else
-      store_g(optr, of64, c, v);
+      store_g(optr, of64, c, v, st.range_flag);
   };
   const uint32_t nC = 1u << rC;
   uint32_t mx = 0;
@@ -1119,7 +1118,7 @@ __device__ __forceinline__ void stream_body(const PStep &d, uint32_t nb, uint32_
         } else if (SCALE) {
           wmax = max(wmax, store_scaled(op, of, c, acc, sh));
         } else {
-          store_g(op, of, c, acc);
+          store_g(op, of, c, acc, d.range_flag);
         }
       }
     }
@@ -1320,7 +1319,7 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
           } else if (SCALE) {
             wmax = max(wmax, store_scaled(op, of, ((uint64_t)row << 8) | t, acc, sh));
           } else {
-            store_g(op, of, ((uint64_t)row << 8) | t, acc);
+            store_g(op, of, ((uint64_t)row << 8) | t, acc, d.range_flag);
           }
         };
         // operand v's runs for `row`, as complex128, at byte `off` of the stage
@@ -1510,7 +1509,7 @@ __device__ __forceinline__ void tiled_body(const PStep &d, uint32_t nb, uint32_t
         } else if (SCALE) {
           wmax = max(wmax, store_scaled(op, of, ((uint64_t)row << 8) | t, acc, sh));
         } else {
-          store_g(op, of, ((uint64_t)row << 8) | t, acc);
+          store_g(op, of, ((uint64_t)row << 8) | t, acc, d.range_flag);
         }
       }
     }
@@ -1636,7 +1635,7 @@ __global__ __launch_bounds__(256) void step_small(const PStep d, uint32_t nb, ui
       }
       if (c == 0) d.out.E[I.qo] = I.esum;
     }
-    store_g((void *)d.out.base, d.out.f64, I.obase + c, acc);
+    store_g((void *)d.out.base, d.out.f64, I.obase + c, acc, d.range_flag);
   }
 }
 constexpr int kStreamMinRank = 8;
@@ -1658,7 +1657,7 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
                                                  qtn_partial *host_out, uint32_t *clear,
                                                  uint64_t nclear, uint64_t keep_lo, uint64_t keep_hi,
                                                  const double2 *dotp, uint64_t dstride, uint32_t dslots,
-                                                 uint32_t *flag_out) {
+                                                 uint32_t *flag, uint32_t *flag_out) {
   __shared__ double sre[256], cre[256], sim[256], cim[256];
   const uint32_t b = blockIdx.x;
   const uint32_t t = threadIdx.x;
@@ -1765,7 +1764,7 @@ __global__ __launch_bounds__(256) void slice_sum(const void *res, uint32_t res64
     if (host_out) {
       host_out[b] = w;
       if (b == 0) {
-        const uint32_t f = atomicExch(&qtn_range_flag, 0u);
+        const uint32_t f = atomicExch(flag, 0u);
         if (flag_out) *flag_out = f;
       }
     }
@@ -2036,6 +2035,7 @@ static void fill_tables(qtn_plan_t *P, DeviceState *D, const ExecPlan &X, std::v
     const Step &S_ = sch.steps[st];
     PStep &d = D->steps[st];
     std::memset(&d, 0, sizeof(d));
+    d.range_flag = (uint32_t *)(D->ws + D->L.flag_off);
     d.nin = (int)S_.in.size();
     d.rC = S_.rC;
     d.nk = S_.nk;
@@ -2257,6 +2257,7 @@ extern "C" int qtn_plan_bind_workspace(qtn_plan_t *P, void *dev_ptr, uint64_t by
   D->ws_bytes = bytes;
   // the exponent words start cleared; the slice sum clears them after each wave
   if (P->precision != QTN_FP64 && L.exp_bytes) HIP_TRY(hipMemset(D->ws + L.data_bytes, 0, L.exp_bytes));
+  HIP_TRY(hipMemset(D->ws + L.flag_off, 0, 4));   // the range word
   D->L = L;
   D->max_slots = max_slots;
   D->lds_bytes = lds_bytes;
@@ -2553,7 +2554,7 @@ static int run_waves(qtn_plan_t *P, DeviceState *D, uint64_t lo, uint64_t hi, hi
                            D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
                            SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0,
                            folded ? (const double2 *)(D->ws + D->L.dot_off) : (const double2 *)nullptr,
-                           (uint64_t)D->L.dot_slots, dot_gx,
+                           (uint64_t)D->L.dot_slots, dot_gx, (uint32_t *)(D->ws + D->L.flag_off),
                            s_lo + S >= hi ? D->flag_dev : (uint32_t *)nullptr);
         first = false;
       } else {
@@ -2696,7 +2697,7 @@ static int run_waves(qtn_plan_t *P, DeviceState *D, uint64_t lo, uint64_t hi, hi
 // results cannot be checked before they are used), in the re-run of a
 // synchronous call that left the form's exponent range, and once that has
 // happened twice in a row; otherwise synchronous calls run without
-// rescaling (qtn_range_flag guards them).
+// rescaling (the workspace's range word guards them).
 static bool scaled_run(const qtn_plan_t *P, const DeviceState *D, bool async) {
   return P->scaled[D->mode] && (async || !D->unscaled || D->force_scaled);
 }
@@ -3177,7 +3178,8 @@ static int batch_enqueue(qtn_plan_t *const *plans, uint32_t n, const uint64_t *l
                        (SCALE && D->L.exp_bytes) ? (uint32_t *)(D->ws + D->L.data_bytes) : (uint32_t *)nullptr,
                        D->L.exp_bytes / 4, SCALE ? (res.exp_off - D->L.data_bytes) / 4 : 0,
                        SCALE ? (res.exp_off - D->L.data_bytes) / 4 + instances(res, B, S) : 0,
-                       (const double2 *)nullptr, (uint64_t)0, 0u, (uint32_t *)nullptr);
+                       (const double2 *)nullptr, (uint64_t)0, 0u, (uint32_t *)(D->ws + D->L.flag_off),
+                       (uint32_t *)nullptr);
   }
   HIP_TRY(hipGetLastError());
   return QTN_OK;
