@@ -50,6 +50,15 @@ def exercise(plan, S, tune=False, tmp=None):
             plan.step_tune(st)
             plan.set_step_tune(st, blocks=512, pair=True)
         plan.contract(0, S)
+    plan.range_state()
+    # the repeat of a contraction counted as out of the 64-bit range
+    os.environ["QTN_RANGE_TEST"] = "1"
+    try:
+        plan.contract(0, S)
+        plan.contract(0, S)
+    finally:
+        del os.environ["QTN_RANGE_TEST"]
+    plan.range_state()
     plan.set_timing(True)
     plan.contract(0, S)
     plan.timing()
